@@ -1,0 +1,153 @@
+"""Merge Path benchmark on one MI355X.
+
+Headline: merge of two sorted uint32 arrays, |A| = |B| = 2^28, keys uniform
+in [0, 2^32) (seed 11), inputs resident in HBM, output preallocated.  One
+step = one full mp_merge call (tile split search + tile merge).  Prints one
+JSON line with the throughput (Gkeys/s merged), the roofline of the dominant
+kernel timed with HIP events on its own stream, and the single-core oracle
+baseline timed on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Gkeys/s merged & % HBM peak (2^28+2^28 u32); learned vs bsearch split time"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def cpu_baseline_merge(A, B, budget_s=10.0):
+    """The oracle's sequential merge on the host, repeated for about budget_s."""
+    import oracle
+    times = []
+    t_all = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        S = oracle.merge(A, B)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_all > budget_s or len(times) >= 8:
+            break
+    times.sort()
+    med = times[len(times) // 2]
+    return S, med, len(times)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--log2n", type=int, default=28, help="log2 of |A| = |B|")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verify", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (the merge shards by diagonal "
+              "splits, but no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import mp_inputs as gen
+    import paper_1406_2628_amd as mp
+
+    torch.cuda.set_device(0)
+    na = nb = 1 << args.log2n
+    seed = 11
+    log(f"bench: generating u32 inputs 2^{args.log2n}+2^{args.log2n} (seed {seed})")
+    A, B = gen.uniform_pair(na, nb, seed)
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    dS = torch.empty(na + nb, dtype=torch.uint32, device="cuda")
+    torch.cuda.synchronize()
+
+    log("bench: timing mp_merge")
+    step = lambda: mp.merge(dA, dB, out=dS)  # noqa: E731
+    mp.timing_enable(False)
+    ms = time_steps(step, args.steps, args.warmup)
+    # per-kernel durations over a second timed region, events on the launch stream
+    mp.timing_enable(True)
+    time_steps(step, args.steps, 0)
+    k_ms, k_n = mp.timing_query("merge_tiles")
+    p_ms, p_n = mp.timing_query("tile_partition")
+    mp.timing_enable(False)
+    kern_ms = k_ms / max(1, k_n)
+    part_ms = p_ms / max(1, p_n)
+
+    n_out = na + nb
+    alg_bytes = n_out * 4 * 2   # every input key read once, every output key written once
+    value = n_out / (ms * 1e-3) / 1e9
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded uniform u32 keys, sorted)",
+        "config": {"workload": f"merge u32 2^{args.log2n}+2^{args.log2n} uniform keys, seed {seed}",
+                   "na": na, "nb": nb},
+        "hbm_frac_step": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "kernel": "merge_tile_kernel",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel_ms": round(kern_ms, 4), "partition_ms": round(part_ms, 4)},
+    }
+
+    if not args.no_verify or not args.no_cpu_baseline:
+        S = dS.cpu().numpy()
+        if args.no_cpu_baseline:
+            import oracle
+            ref = oracle.merge(A, B)
+        else:
+            log("bench: oracle merge on the host (cpu baseline + verification)")
+            ref, cpu_s, reps = cpu_baseline_merge(A, B)
+            result["cpu_baseline"] = {
+                "value": round(n_out / cpu_s / 1e9, 4), "unit": "Gkeys/s", "cores": 1,
+                "kind": "oracle",
+                "sample": f"full workload (2^{args.log2n}+2^{args.log2n} u32), median of {reps} runs, "
+                          f"1 of {os.cpu_count()} host threads"}
+        result["bit_exact"] = bool(S.tobytes() == ref.tobytes())
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

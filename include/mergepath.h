@@ -1,0 +1,162 @@
+/*
+ * mergepath.h -- C ABI of the MI355X (gfx950) Merge Path library.
+ *
+ * The operations follow the problem statement of Green, Odeh and Birk,
+ * "Merge Path - A Visually Intuitive Approach to Parallel Merging":
+ * A and B are sorted ascending and may differ in length (section 2.1); S is
+ * their merge; the split on cross diagonal d is where the Merge Path crosses
+ * that diagonal (Lemma 8, Theorem 9), found by a binary search along it
+ * (Algorithm 2, Theorem 14); pairs cut at any diagonals merge independently
+ * and concatenate to S (Theorem 5, Corollary 6).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers: every array argument is a DEVICE pointer owned by the caller,
+ *    unless the comment says "host".  The library never frees caller memory.
+ *    Arrays must be aligned to their element size.
+ *  - Layout: arrays are dense, one element after the other (structure of
+ *    arrays: keys and values are separate arrays).
+ *  - Sizes are element counts (int64_t); a size of 0 is a valid no-op and
+ *    the matching pointer may then be NULL.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls are asynchronous: they return once work is enqueued.
+ *    Argument errors are reported before anything is enqueued; launch errors
+ *    are reported as MP_ERR_HIP; faults during execution surface at the
+ *    caller's next synchronisation.
+ *  - Preconditions NOT checked on the device: inputs sorted ascending under
+ *    the key order, and float keys free of NaN.  Violating them gives an
+ *    unspecified result but every memory access stays in bounds.
+ *  - Key order: MP_U32 and MP_U64 unsigned, MP_I32 signed, MP_F32 IEEE
+ *    (-0.0 and +0.0 are equal keys).  Ties take A first (section 2.1: the
+ *    path steps right, taking B[j], only when A[i] > B[j]), so every merge
+ *    is stable with A before B, and the output is bit-exact.
+ *  - Output must not overlap any input (MP_ERR_OVERLAP): no in-place merge.
+ *  - On any status other than MP_OK, mp_last_error() returns a message
+ *    (per thread).
+ *  - Thread safety: calls without a handle are thread-safe; a learned
+ *    partitioner handle must not be used by two threads at once.
+ */
+#ifndef MERGEPATH_H
+#define MERGEPATH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MP_NONE = 0, /* no values (keys-only) */
+  MP_U32 = 1,
+  MP_I32 = 2,
+  MP_U64 = 3,
+  MP_F32 = 4
+} mp_dtype;
+
+typedef enum {
+  MP_OK = 0,
+  MP_ERR_INVALID_ARG = -1, /* negative size, NULL pointer with size > 0, bad option */
+  MP_ERR_UNSUPPORTED = -2, /* dtype or dtype combination not provided */
+  MP_ERR_OVERLAP = -3,     /* an output range overlaps an input range */
+  MP_ERR_WORKSPACE = -4,   /* workspace NULL or smaller than required */
+  MP_ERR_HIP = -5,         /* the HIP runtime reported an error */
+  MP_ERR_STATE = -6        /* handle not trained, or file format mismatch */
+} mp_status;
+
+/* Message describing the most recent non-OK status on this thread. */
+const char *mp_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int mp_version(void);
+
+/*
+ * mp_partition -- split on each requested cross diagonal (Algorithm 2,
+ * Theorem 9, Theorem 14).
+ *   kt        key dtype (MP_U32, MP_I32, MP_U64, MP_F32)
+ *   A, na     sorted keys of A;  B, nb  sorted keys of B
+ *   diag      n_diag diagonals (int64), each in [0, na+nb], any order;
+ *             values outside that range are clamped into it
+ *   a_split   n_diag int64 outputs: a_split[k] is the unique a with
+ *             b = diag[k] - a satisfying  A[a-1] <= B[b]  and  B[b-1] < A[a]
+ *             (terms whose index falls outside A or B count as satisfied).
+ *             The pair (A[a_k, a_{k+1}), B[b_k, b_{k+1})) merges to
+ *             S[diag[k], diag[k+1]) for consecutive diagonals (Corollary 6).
+ * At most ceil(log2(min(na, nb) + 1)) search steps per diagonal.
+ */
+mp_status mp_partition(mp_dtype kt, const void *A, int64_t na, const void *B,
+                       int64_t nb, const int64_t *diag, int64_t n_diag,
+                       int64_t *a_split, void *stream);
+
+/*
+ * mp_merge -- S = merge of A and B (Algorithm 1: equal-length output tiles,
+ * each tile's split by Algorithm 2, tiles merged independently).
+ *   S   na+nb keys of dtype kt, must not overlap A or B.
+ */
+mp_status mp_merge(mp_dtype kt, const void *A, int64_t na, const void *B,
+                   int64_t nb, void *S, void *stream);
+
+/*
+ * mp_merge_kv -- key-value merge: keys as mp_merge; each value travels with
+ * its key (stable: equal keys keep A's values before B's, each input's own
+ * order preserved).
+ *   vt   value dtype: any 4-byte type (MP_U32, MP_I32, MP_F32), moved as bits
+ *   Ak/Av, na and Bk/Bv, nb   keys and values of A and of B
+ *   Sk/Sv  na+nb outputs; neither may overlap an input nor each other.
+ */
+mp_status mp_merge_kv(mp_dtype kt, mp_dtype vt, const void *Ak, const void *Av,
+                      int64_t na, const void *Bk, const void *Bv, int64_t nb,
+                      void *Sk, void *Sv, void *stream);
+
+/*
+ * mp_merge_batched -- many independent merges in one launch (Corollary 6
+ * applied to a concatenation of pairs; Corollary 7 load balance over the
+ * global output index).
+ *   A, a_off  concatenated A_k; a_off has n_pairs+1 int64 entries (device),
+ *             a_off[0] = 0, non-decreasing; A_k = A[a_off[k], a_off[k+1])
+ *   B, b_off  likewise for B_k
+ *   S         a_off[n]+b_off[n] outputs; pair k is written to
+ *             S[a_off[k]+b_off[k], a_off[k+1]+b_off[k+1])
+ *   total_a, total_b   a_off[n_pairs] and b_off[n_pairs] (host copies,
+ *             used to size the launch; must match the device offsets)
+ *   ws, ws_bytes  device workspace of at least
+ *             mp_merge_batched_workspace_bytes(kt, n_pairs, total_a+total_b)
+ * Offsets are not validated on the device; non-monotone offsets give an
+ * unspecified result with in-bounds accesses.
+ */
+size_t mp_merge_batched_workspace_bytes(mp_dtype kt, int64_t n_pairs,
+                                        int64_t total);
+mp_status mp_merge_batched(mp_dtype kt, const void *A, const int64_t *a_off,
+                           const void *B, const int64_t *b_off,
+                           int64_t n_pairs, int64_t total_a, int64_t total_b,
+                           void *S, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * mp_sort -- stable merge sort in place (section 3: sorted blocks, then
+ * log2 rounds of merges of adjacent runs, left run as A; section 4.2:
+ * blocks sized to on-chip memory first).
+ *   keys, n     keys of dtype kt, sorted in place
+ *   vt, vals    MP_NONE and NULL, or a 4-byte value dtype and n values
+ *               permuted with their keys
+ *   ws          device workspace of at least mp_sort_workspace_bytes(kt, vt, n)
+ */
+size_t mp_sort_workspace_bytes(mp_dtype kt, mp_dtype vt, int64_t n);
+mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Kernel timing (profiling aid, off by default).  While enabled, every kernel
+ * the library launches is bracketed by two HIP events recorded on the launch
+ * stream.  mp_timing_query synchronises on the recorded events and returns,
+ * for the kernel family `name` (e.g. "merge_tiles", "partition"), the summed
+ * duration in milliseconds and the number of launches since the last reset.
+ * Returns MP_ERR_INVALID_ARG for NULL outputs, MP_ERR_HIP on event errors.
+ */
+mp_status mp_timing_enable(int on);
+mp_status mp_timing_reset(void);
+mp_status mp_timing_query(const char *name, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MERGEPATH_H */

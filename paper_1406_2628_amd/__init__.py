@@ -1,0 +1,191 @@
+"""Merge Path on MI355X (gfx950): Python binding of ``libmergepath.so``.
+
+Argument marshalling only: every step of every operation runs in the HIP
+kernels of the C-ABI library (``include/mergepath.h``).  PyTorch supplies
+device memory and the current stream; it computes nothing here.  If the
+library is not built, every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmergepath.so")
+
+MP_NONE, MP_U32, MP_I32, MP_U64, MP_F32 = 0, 1, 2, 3, 4
+_STATUS = {0: "MP_OK", -1: "MP_ERR_INVALID_ARG", -2: "MP_ERR_UNSUPPORTED",
+           -3: "MP_ERR_OVERLAP", -4: "MP_ERR_WORKSPACE", -5: "MP_ERR_HIP",
+           -6: "MP_ERR_STATE"}
+TORCH_TO_MP = {torch.uint32: MP_U32, torch.int32: MP_I32, torch.uint64: MP_U64,
+               torch.float32: MP_F32}
+
+_lib = None
+
+
+class MergePathError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1406_2628_amd.build` (no CPU fallback exists)")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def _declare(L):
+    p, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+    sig = {
+        "mp_last_error": ([], ctypes.c_char_p),
+        "mp_version": ([], i32),
+        "mp_partition": ([i32, p, i64, p, i64, p, i64, p, p], i32),
+        "mp_merge": ([i32, p, i64, p, i64, p, p], i32),
+        "mp_merge_kv": ([i32, i32, p, p, i64, p, p, i64, p, p, p], i32),
+        "mp_merge_batched_workspace_bytes": ([i32, i64, i64], sz),
+        "mp_merge_batched": ([i32, p, p, p, p, i64, i64, i64, p, p, sz, p], i32),
+        "mp_sort_workspace_bytes": ([i32, i32, i64], sz),
+        "mp_sort": ([i32, i32, p, p, i64, p, sz, p], i32),
+        "mp_timing_enable": ([i32], i32),
+        "mp_timing_reset": ([], i32),
+        "mp_timing_query": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_int64)], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes, f.restype = args, res
+    return L
+
+
+def timing_enable(on: bool = True):
+    _check(lib().mp_timing_enable(1 if on else 0))
+    _check(lib().mp_timing_reset())
+
+
+def timing_query(name: str):
+    """(total_ms, launches) of kernel family ``name`` since the last reset."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().mp_timing_query(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def last_error() -> str:
+    return lib().mp_last_error().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise MergePathError(status, last_error())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _key_dtype(*ts) -> int:
+    dt = ts[0].dtype
+    for t in ts:
+        if t.dtype != dt:
+            raise TypeError("key arrays must share one dtype")
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("arrays must be contiguous device tensors")
+    if dt not in TORCH_TO_MP:
+        raise TypeError(f"unsupported key dtype {dt}")
+    return TORCH_TO_MP[dt]
+
+
+def _val_dtype(*ts) -> int:
+    dt = ts[0].dtype
+    for t in ts:
+        if t.dtype != dt or t.element_size() != 4:
+            raise TypeError("values must share one 4-byte dtype")
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("arrays must be contiguous device tensors")
+    return {torch.uint32: MP_U32, torch.int32: MP_I32, torch.float32: MP_F32}[dt]
+
+
+def partition(A: torch.Tensor, B: torch.Tensor, diag: torch.Tensor,
+              out: torch.Tensor | None = None) -> torch.Tensor:
+    """Split (count of A elements) on each cross diagonal in ``diag`` (int64)."""
+    kt = _key_dtype(A, B)
+    if out is None:
+        out = torch.empty(diag.numel(), dtype=torch.int64, device=A.device)
+    _check(lib().mp_partition(kt, _ptr(A), A.numel(), _ptr(B), B.numel(), _ptr(diag),
+                              diag.numel(), _ptr(out), _stream(A.device)))
+    return out
+
+
+def merge(A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    kt = _key_dtype(A, B)
+    if out is None:
+        out = torch.empty(A.numel() + B.numel(), dtype=A.dtype, device=A.device)
+    _check(lib().mp_merge(kt, _ptr(A), A.numel(), _ptr(B), B.numel(), _ptr(out),
+                          _stream(A.device)))
+    return out
+
+
+def merge_kv(Ak, Av, Bk, Bv, out_k=None, out_v=None):
+    kt = _key_dtype(Ak, Bk)
+    vt = _val_dtype(Av, Bv)
+    if Av.numel() != Ak.numel() or Bv.numel() != Bk.numel():
+        raise ValueError("each value array must match its key array")
+    n = Ak.numel() + Bk.numel()
+    if out_k is None:
+        out_k = torch.empty(n, dtype=Ak.dtype, device=Ak.device)
+    if out_v is None:
+        out_v = torch.empty(n, dtype=Av.dtype, device=Ak.device)
+    _check(lib().mp_merge_kv(kt, vt, _ptr(Ak), _ptr(Av), Ak.numel(), _ptr(Bk), _ptr(Bv),
+                             Bk.numel(), _ptr(out_k), _ptr(out_v), _stream(Ak.device)))
+    return out_k, out_v
+
+
+def merge_batched_workspace_bytes(dtype: torch.dtype, n_pairs: int, total: int) -> int:
+    return lib().mp_merge_batched_workspace_bytes(TORCH_TO_MP[dtype], n_pairs, total)
+
+
+def merge_batched(A, a_off, B, b_off, total_a: int | None = None, total_b: int | None = None,
+                  out=None, ws=None):
+    """Independent merges of (A[a_off[k]:a_off[k+1]], B[b_off[k]:b_off[k+1]])."""
+    kt = _key_dtype(A, B)
+    n_pairs = a_off.numel() - 1
+    total_a = A.numel() if total_a is None else total_a
+    total_b = B.numel() if total_b is None else total_b
+    if out is None:
+        out = torch.empty(total_a + total_b, dtype=A.dtype, device=A.device)
+    need = merge_batched_workspace_bytes(A.dtype, n_pairs, total_a + total_b)
+    if ws is None and need:
+        ws = torch.empty(need, dtype=torch.uint8, device=A.device)
+    _check(lib().mp_merge_batched(kt, _ptr(A), _ptr(a_off), _ptr(B), _ptr(b_off), n_pairs,
+                                  total_a, total_b, _ptr(out), _ptr(ws),
+                                  0 if ws is None else ws.numel(), _stream(A.device)))
+    return out
+
+
+def sort_workspace_bytes(key_dtype: torch.dtype, val_dtype: torch.dtype | None, n: int) -> int:
+    vt = MP_NONE if val_dtype is None else {torch.uint32: MP_U32, torch.int32: MP_I32,
+                                             torch.float32: MP_F32}[val_dtype]
+    return lib().mp_sort_workspace_bytes(TORCH_TO_MP[key_dtype], vt, n)
+
+
+def sort(keys: torch.Tensor, vals: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """Stable in-place merge sort of ``keys`` (and ``vals`` with them)."""
+    kt = _key_dtype(keys)
+    vt = MP_NONE if vals is None else _val_dtype(vals)
+    need = sort_workspace_bytes(keys.dtype, None if vals is None else vals.dtype, keys.numel())
+    if ws is None and need:
+        ws = torch.empty(need, dtype=torch.uint8, device=keys.device)
+    _check(lib().mp_sort(kt, vt, _ptr(keys), _ptr(vals), keys.numel(), _ptr(ws),
+                         0 if ws is None else ws.numel(), _stream(keys.device)))
+    return keys if vals is None else (keys, vals)

@@ -1,0 +1,209 @@
+// C ABI layer: host-side argument validation, dtype dispatch and launches.
+// Validation never touches device memory, so every argument error is
+// reported before any work is enqueued.
+#include <mutex>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+#include <vector>
+
+#include "mp_internal.h"
+
+namespace mp {
+namespace {
+
+thread_local char g_err[512] = "";
+
+mp_status fail(mp_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+mp_status hip_fail(hipError_t e, const char *what) {
+  return fail(MP_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_key(mp_dtype t) {
+  return t == MP_U32 || t == MP_I32 || t == MP_U64 || t == MP_F32;
+}
+bool is_val32(mp_dtype t) { return t == MP_U32 || t == MP_I32 || t == MP_F32; }
+
+struct Range {
+  uintptr_t lo, hi;
+};
+Range span(const void *p, int64_t n, size_t es) {
+  const uintptr_t b = (uintptr_t)p;
+  return Range{b, b + (uintptr_t)n * es};
+}
+bool overlaps(Range x, Range y) {
+  return x.lo < x.hi && y.lo < y.hi && x.lo < y.hi && y.lo < x.hi;
+}
+
+mp_status check_array(const void *p, int64_t n, size_t es, const char *name) {
+  if (n < 0) return fail(MP_ERR_INVALID_ARG, "%s: negative size %lld", name, (long long)n);
+  if (n > 0 && p == nullptr) return fail(MP_ERR_INVALID_ARG, "%s: NULL pointer with size %lld", name, (long long)n);
+  if (n > 0 && ((uintptr_t)p % es) != 0) return fail(MP_ERR_INVALID_ARG, "%s: pointer not aligned to %zu bytes", name, es);
+  return MP_OK;
+}
+
+}  // namespace
+
+void *device_scratch(size_t bytes, hipError_t *err) {
+  struct Slot {
+    void *p = nullptr;
+    size_t size = 0;
+  };
+  static std::mutex mu;
+  static std::vector<Slot> slots;
+  int dev = 0;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)slots.size() <= dev) slots.resize(dev + 1);
+  Slot &s = slots[dev];
+  if (s.size < bytes) {
+    if (s.p) {
+      *err = hipDeviceSynchronize();
+      if (*err != hipSuccess) return nullptr;
+      (void)hipFree(s.p);
+      s.p = nullptr;
+      s.size = 0;
+    }
+    *err = hipMalloc(&s.p, bytes);
+    if (*err != hipSuccess) return nullptr;
+    s.size = bytes;
+  }
+  *err = hipSuccess;
+  return s.p;
+}
+
+}  // namespace mp
+
+using namespace mp;
+
+extern "C" {
+
+const char *mp_last_error(void) { return g_err; }
+
+int mp_version(void) { return 100; }
+
+mp_status mp_partition(mp_dtype kt, const void *A, int64_t na, const void *B,
+                       int64_t nb, const int64_t *diag, int64_t n_diag,
+                       int64_t *a_split, void *stream) {
+  if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "mp_partition: unsupported key dtype %d", (int)kt);
+  const size_t es = dtype_size(kt);
+  mp_status st;
+  if ((st = check_array(A, na, es, "A")) != MP_OK) return st;
+  if ((st = check_array(B, nb, es, "B")) != MP_OK) return st;
+  if ((st = check_array(diag, n_diag, 8, "diag")) != MP_OK) return st;
+  if ((st = check_array(a_split, n_diag, 8, "a_split")) != MP_OK) return st;
+  const Range out = span(a_split, n_diag, 8);
+  if (overlaps(out, span(A, na, es)) || overlaps(out, span(B, nb, es)) ||
+      overlaps(out, span(diag, n_diag, 8)))
+    return fail(MP_ERR_OVERLAP, "mp_partition: a_split overlaps an input");
+  if (n_diag == 0) return MP_OK;
+  hipError_t e = hipSuccess;
+  dispatch_key(kt, [&](auto k) {
+    using K = decltype(k);
+    KernelTimer timer("partition", (hipStream_t)stream);
+    e = launch_partition<K>((const K *)A, na, (const K *)B, nb, diag, 0, n_diag,
+                            a_split, (hipStream_t)stream);
+  });
+  return e == hipSuccess ? MP_OK : hip_fail(e, "mp_partition launch");
+}
+
+static mp_status merge_common(const char *fn, mp_dtype kt, mp_dtype vt,
+                              const void *Ak, const void *Av, int64_t na,
+                              const void *Bk, const void *Bv, int64_t nb,
+                              void *Sk, void *Sv, void *stream) {
+  if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported key dtype %d", fn, (int)kt);
+  const bool kv = vt != MP_NONE;
+  if (kv && !is_val32(vt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported value dtype %d", fn, (int)vt);
+  const size_t es = dtype_size(kt);
+  mp_status st;
+  if ((st = check_array(Ak, na, es, "A")) != MP_OK) return st;
+  if ((st = check_array(Bk, nb, es, "B")) != MP_OK) return st;
+  if (na > INT64_MAX - nb) return fail(MP_ERR_INVALID_ARG, "%s: na + nb overflows", fn);
+  const int64_t n = na + nb;
+  if ((st = check_array(Sk, n, es, "S")) != MP_OK) return st;
+  const Range rs = span(Sk, n, es);
+  if (overlaps(rs, span(Ak, na, es)) || overlaps(rs, span(Bk, nb, es)))
+    return fail(MP_ERR_OVERLAP, "%s: output keys overlap an input", fn);
+  if (kv) {
+    if ((st = check_array(Av, na, 4, "Av")) != MP_OK) return st;
+    if ((st = check_array(Bv, nb, 4, "Bv")) != MP_OK) return st;
+    if ((st = check_array(Sv, n, 4, "Sv")) != MP_OK) return st;
+    const Range rv = span(Sv, n, 4);
+    if (overlaps(rv, span(Av, na, 4)) || overlaps(rv, span(Bv, nb, 4)) ||
+        overlaps(rv, span(Ak, na, es)) || overlaps(rv, span(Bk, nb, es)) ||
+        overlaps(rv, rs) || overlaps(rs, span(Av, na, 4)) ||
+        overlaps(rs, span(Bv, nb, 4)))
+      return fail(MP_ERR_OVERLAP, "%s: an output overlaps an input or the other output", fn);
+  }
+  if (n == 0) return MP_OK;
+
+  const TileCfg cfg = default_tile_cfg(es, kv);
+  const int64_t T = (int64_t)cfg.nt * cfg.vt;
+  const int64_t n_tiles = (n + T - 1) / T;
+  hipError_t e = hipSuccess;
+  int64_t *splits = (int64_t *)device_scratch((size_t)(n_tiles + 1) * 8, &e);
+  if (!splits) return hip_fail(e, "workspace allocation");
+  hipStream_t s = (hipStream_t)stream;
+  dispatch_key(kt, [&](auto k) {
+    using K = decltype(k);
+    {
+      KernelTimer timer("tile_partition", s);
+      e = launch_partition<K>((const K *)Ak, na, (const K *)Bk, nb, nullptr, T,
+                              n_tiles + 1, splits, s);
+    }
+    if (e != hipSuccess) return;
+    KernelTimer timer("merge_tiles", s);
+    e = launch_merge_tiles<K>(cfg, (const K *)Ak, (const uint32_t *)Av, na,
+                              (const K *)Bk, (const uint32_t *)Bv, nb, (K *)Sk,
+                              kv ? (uint32_t *)Sv : nullptr, splits, s);
+  });
+  return e == hipSuccess ? MP_OK : hip_fail(e, "merge launch");
+}
+
+mp_status mp_merge(mp_dtype kt, const void *A, int64_t na, const void *B,
+                   int64_t nb, void *S, void *stream) {
+  return merge_common("mp_merge", kt, MP_NONE, A, nullptr, na, B, nullptr, nb, S,
+                      nullptr, stream);
+}
+
+mp_status mp_merge_kv(mp_dtype kt, mp_dtype vt, const void *Ak, const void *Av,
+                      int64_t na, const void *Bk, const void *Bv, int64_t nb,
+                      void *Sk, void *Sv, void *stream) {
+  if (vt == MP_NONE) return fail(MP_ERR_INVALID_ARG, "mp_merge_kv: value dtype is MP_NONE");
+  return merge_common("mp_merge_kv", kt, vt, Ak, Av, na, Bk, Bv, nb, Sk, Sv, stream);
+}
+
+size_t mp_merge_batched_workspace_bytes(mp_dtype kt, int64_t n_pairs, int64_t total) {
+  (void)kt; (void)n_pairs; (void)total;
+  return 0;
+}
+
+mp_status mp_merge_batched(mp_dtype kt, const void *A, const int64_t *a_off,
+                           const void *B, const int64_t *b_off, int64_t n_pairs,
+                           int64_t total_a, int64_t total_b, void *S, void *ws,
+                           size_t ws_bytes, void *stream) {
+  (void)kt; (void)A; (void)a_off; (void)B; (void)b_off; (void)n_pairs;
+  (void)total_a; (void)total_b; (void)S; (void)ws; (void)ws_bytes; (void)stream;
+  return fail(MP_ERR_UNSUPPORTED, "mp_merge_batched: not built yet");
+}
+
+size_t mp_sort_workspace_bytes(mp_dtype kt, mp_dtype vt, int64_t n) {
+  (void)kt; (void)vt; (void)n;
+  return 0;
+}
+
+mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
+                  void *ws, size_t ws_bytes, void *stream) {
+  (void)kt; (void)vt; (void)keys; (void)vals; (void)n; (void)ws; (void)ws_bytes; (void)stream;
+  return fail(MP_ERR_UNSUPPORTED, "mp_sort: not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// Device-side building blocks of the Merge Path kernels (gfx950, wave64).
+//
+// Notation follows the paper: A and B are the sorted inputs, a split on cross
+// diagonal d is the pair (a, b = d - a) where the Merge Path crosses that
+// diagonal.  The split is the smallest a on the diagonal for which
+//     B[b-1] < A[a]                     (the path does not step right there)
+// holds, with terms outside A or B counting as true; at that a the second
+// condition of Algorithm 2, A[a-1] <= B[b], holds as well, and the split is
+// unique (Corollary 12, Proposition 13).  Every search below is a lower-bound
+// binary search for that predicate (Algorithm 2 with its search interval
+// clamped to the diagonal's extent inside the grid, and floor midpoints).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mp {
+
+// Bounds of the candidate a on diagonal d of an na x nb grid.
+template <typename I>
+__device__ __forceinline__ void diag_range(I d, I na, I nb, I &lo, I &hi) {
+  lo = d > nb ? d - nb : 0;
+  hi = d < na ? d : na;
+}
+
+// Lower-bound search for the split on diagonal d over arrays reachable
+// through the accessors ga(i) (A) and gb(j) (B).  Only indices in
+// [lo, hi) of A and [d-hi, d-1-lo] of B are probed.
+template <typename I, typename GA, typename GB>
+__device__ __forceinline__ I split_search(I d, I lo, I hi, GA ga, GB gb) {
+  while (lo < hi) {
+    I mid = lo + ((hi - lo) >> 1);
+    if (gb(d - 1 - mid) < ga(mid))
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+// Serial merge of VT outputs from a split, entirely in LDS (Lemma 1; the
+// loser of each compare stays in a register so each step reads one key).
+//   keys: LDS array holding the A window at [0, wa) and the B window at
+//         [wa, wa + wb); index wa + wb must be readable (one padding slot).
+//   ai, bi: LDS positions of the next A and B keys (bi already offset by wa).
+//   n_steps: how many outputs this lane produces (<= VT).
+// On return out[i] holds the keys and src[i] their LDS positions.
+template <typename K, int VT>
+__device__ __forceinline__ void serial_merge(const K *keys, int ai, int bi,
+                                             int a_end, int b_end, int n_steps,
+                                             K (&out)[VT], int (&src)[VT]) {
+  K ka = keys[ai];
+  K kb = keys[bi];
+#pragma unroll
+  for (int i = 0; i < VT; ++i) {
+    if (i < n_steps) {
+      const bool take_b = (bi < b_end) && (ai >= a_end || kb < ka);
+      out[i] = take_b ? kb : ka;
+      src[i] = take_b ? bi : ai;
+      ai += take_b ? 0 : 1;
+      bi += take_b ? 1 : 0;
+      const K nxt = keys[take_b ? bi : ai];
+      ka = take_b ? ka : nxt;
+      kb = take_b ? nxt : kb;
+    }
+  }
+}
+
+}  // namespace mp

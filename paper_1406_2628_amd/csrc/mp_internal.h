@@ -1,0 +1,73 @@
+// Host-side internal interface between the C ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mergepath.h"
+
+namespace mp {
+
+// Calls f(K{}) with a value of the key type named by kt; returns false for
+// an unknown dtype.
+template <typename F>
+bool dispatch_key(mp_dtype kt, F &&f) {
+  switch (kt) {
+    case MP_U32: f(uint32_t{}); return true;
+    case MP_I32: f(int32_t{}); return true;
+    case MP_U64: f(uint64_t{}); return true;
+    case MP_F32: f(float{}); return true;
+    default: return false;
+  }
+}
+
+inline size_t dtype_size(mp_dtype t) {
+  switch (t) {
+    case MP_U32: case MP_I32: case MP_F32: return 4;
+    case MP_U64: return 8;
+    default: return 0;
+  }
+}
+
+// Tile geometry of the per-tile merge: NT lanes x VT outputs per lane.
+struct TileCfg {
+  int nt;
+  int vt;
+};
+
+// Grid-level split search on explicit diagonals (diag != nullptr) or on the
+// equispaced diagonals k * tile clamped to na + nb (diag == nullptr).
+template <typename K>
+hipError_t launch_partition(const K *A, int64_t na, const K *B, int64_t nb,
+                            const int64_t *diag, int64_t tile, int64_t n_diag,
+                            int64_t *a_split, hipStream_t s);
+
+// Per-tile merge of T = nt * vt outputs per workgroup, given the splits of
+// every tile boundary (n_tiles + 1 entries).  Av/Bv/Sv may be null (keys only).
+template <typename K>
+hipError_t launch_merge_tiles(TileCfg cfg, const K *A, const uint32_t *Av,
+                              int64_t na, const K *B, const uint32_t *Bv,
+                              int64_t nb, K *S, uint32_t *Sv,
+                              const int64_t *a_split, hipStream_t s);
+
+TileCfg default_tile_cfg(size_t key_bytes, bool kv);
+
+// Brackets one kernel launch with HIP events on its stream while timing is
+// enabled (mp_timing_enable); does nothing otherwise.
+class KernelTimer {
+ public:
+  KernelTimer(const char *name, hipStream_t s);
+  ~KernelTimer();
+
+ private:
+  const char *name_;
+  hipStream_t s_;
+  hipEvent_t start_ = nullptr;
+};
+
+// Per-device scratch buffer owned by the library (grown on demand, kept until
+// the process ends).
+void *device_scratch(size_t bytes, hipError_t *err);
+
+}  // namespace mp

@@ -1,0 +1,169 @@
+// Grid-level split search and the per-tile merge (Algorithms 1 and 2).
+//
+// launch_partition: one lane per diagonal, lower-bound binary search along
+//   the cross diagonal (Algorithm 2; Theorem 14 bounds the steps by
+//   ceil(log2(min(na, nb) + 1))).
+// merge_tile_kernel: one workgroup per output tile of T = NT * VT elements.
+//   The tile's A and B windows are exactly the pair cut by two consecutive
+//   splits (Theorem 5); they are staged in LDS, every lane finds its own
+//   split inside the tile at local diagonal lane * VT (the same search, now
+//   over LDS), merges VT outputs serially, and the tile is written back with
+//   coalesced stores through an LDS transpose.
+#include "mp_device.h"
+#include "mp_internal.h"
+
+namespace mp {
+
+template <typename K>
+__global__ void partition_kernel(const K *__restrict__ A, int64_t na,
+                                 const K *__restrict__ B, int64_t nb,
+                                 const int64_t *__restrict__ diag, int64_t tile,
+                                 int64_t n_diag, int64_t *__restrict__ a_split) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_diag) return;
+  const int64_t n = na + nb;
+  int64_t d = diag ? diag[k] : k * tile;
+  d = d < 0 ? 0 : (d > n ? n : d);
+  int64_t lo, hi;
+  diag_range<int64_t>(d, na, nb, lo, hi);
+  a_split[k] = split_search<int64_t>(
+      d, lo, hi, [&](int64_t i) { return A[i]; },
+      [&](int64_t j) { return B[j]; });
+}
+
+template <typename K>
+hipError_t launch_partition(const K *A, int64_t na, const K *B, int64_t nb,
+                            const int64_t *diag, int64_t tile, int64_t n_diag,
+                            int64_t *a_split, hipStream_t s) {
+  if (n_diag <= 0) return hipSuccess;
+  constexpr int kThreads = 256;
+  const int64_t blocks = (n_diag + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(partition_kernel<K>, dim3((unsigned)blocks), dim3(kThreads),
+                     0, s, A, na, B, nb, diag, tile, n_diag, a_split);
+  return hipGetLastError();
+}
+
+template <typename K, bool KV, int NT, int VT>
+__global__ __launch_bounds__(NT) void merge_tile_kernel(
+    const K *__restrict__ A, const uint32_t *__restrict__ Av, int64_t na,
+    const K *__restrict__ B, const uint32_t *__restrict__ Bv, int64_t nb,
+    K *__restrict__ S, uint32_t *__restrict__ Sv,
+    const int64_t *__restrict__ a_split) {
+  constexpr int T = NT * VT;
+  __shared__ K keys[T + 1];
+  __shared__ uint32_t vals[KV ? T : 1];
+  const int tid = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t n_all = na + nb;
+  const int64_t d0 = tile * T;
+  const int64_t d1 = d0 + T < n_all ? d0 + T : n_all;
+  const int64_t a0 = a_split[tile], a1 = a_split[tile + 1];
+  const int64_t b0 = d0 - a0;
+  const int n = (int)(d1 - d0);
+  // For sorted inputs a1 - a0 already lies in this range; the clamp only
+  // keeps every access in bounds when the sortedness precondition is broken.
+  int64_t wa64 = a1 - a0;
+  const int64_t wa_lo = d1 - nb - a0 > 0 ? d1 - nb - a0 : 0;
+  const int64_t wa_hi = na - a0 < (int64_t)n ? na - a0 : (int64_t)n;
+  wa64 = wa64 < wa_lo ? wa_lo : (wa64 > wa_hi ? wa_hi : wa64);
+  const int wa = (int)wa64, wb = n - wa;
+
+  // Stage the pair (A[a0, a1), B[b0, b1)) back to back in LDS.
+  for (int i = tid; i < n; i += NT) {
+    if (i < wa) {
+      keys[i] = A[a0 + i];
+      if constexpr (KV) vals[i] = Av[a0 + i];
+    } else {
+      keys[i] = B[b0 + i - wa];
+      if constexpr (KV) vals[i] = Bv[b0 + i - wa];
+    }
+  }
+  __syncthreads();
+
+  // Lane split at local diagonal tid * VT, then VT serial steps.
+  const int dl = tid * VT < n ? tid * VT : n;
+  int lo, hi;
+  diag_range<int>(dl, wa, wb, lo, hi);
+  const int a = split_search<int>(
+      dl, lo, hi, [&](int i) { return keys[i]; },
+      [&](int j) { return keys[wa + j]; });
+  const int steps = n - dl < VT ? n - dl : VT;
+  K out[VT];
+  int src[VT];
+  serial_merge<K, VT>(keys, a, wa + dl - a, wa, n, steps, out, src);
+  uint32_t ov[VT];
+  if constexpr (KV) {
+#pragma unroll
+    for (int i = 0; i < VT; ++i)
+      if (i < steps) ov[i] = vals[src[i]];
+  }
+  __syncthreads();
+
+  // Transpose through LDS so that the global stores are coalesced.
+#pragma unroll
+  for (int i = 0; i < VT; ++i) {
+    if (i < steps) {
+      keys[tid * VT + i] = out[i];
+      if constexpr (KV) vals[tid * VT + i] = ov[i];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += NT) {
+    S[d0 + i] = keys[i];
+    if constexpr (KV) Sv[d0 + i] = vals[i];
+  }
+}
+
+TileCfg default_tile_cfg(size_t key_bytes, bool kv) {
+  (void)key_bytes;
+  (void)kv;
+  return TileCfg{256, 16};
+}
+
+template <typename K, bool KV, int NT, int VT>
+static hipError_t launch_tiles_impl(const K *A, const uint32_t *Av, int64_t na,
+                                    const K *B, const uint32_t *Bv, int64_t nb,
+                                    K *S, uint32_t *Sv, const int64_t *a_split,
+                                    hipStream_t s) {
+  constexpr int64_t T = NT * VT;
+  const int64_t n_tiles = (na + nb + T - 1) / T;
+  if (n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL((merge_tile_kernel<K, KV, NT, VT>), dim3((unsigned)n_tiles),
+                     dim3(NT), 0, s, A, Av, na, B, Bv, nb, S, Sv, a_split);
+  return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_merge_tiles(TileCfg cfg, const K *A, const uint32_t *Av,
+                              int64_t na, const K *B, const uint32_t *Bv,
+                              int64_t nb, K *S, uint32_t *Sv,
+                              const int64_t *a_split, hipStream_t s) {
+  const bool kv = Sv != nullptr;
+#define MP_TILE_CASE(NT_, VT_)                                                \
+  if (cfg.nt == NT_ && cfg.vt == VT_)                                         \
+    return kv ? launch_tiles_impl<K, true, NT_, VT_>(A, Av, na, B, Bv, nb, S, \
+                                                     Sv, a_split, s)          \
+              : launch_tiles_impl<K, false, NT_, VT_>(A, Av, na, B, Bv, nb,   \
+                                                      S, Sv, a_split, s);
+  MP_TILE_CASE(256, 16)
+  MP_TILE_CASE(256, 15)
+  MP_TILE_CASE(256, 8)
+  MP_TILE_CASE(128, 16)
+#undef MP_TILE_CASE
+  return hipErrorInvalidValue;
+}
+
+#define MP_INSTANTIATE(K)                                                      \
+  template hipError_t launch_partition<K>(const K *, int64_t, const K *,       \
+                                          int64_t, const int64_t *, int64_t,   \
+                                          int64_t, int64_t *, hipStream_t);    \
+  template hipError_t launch_merge_tiles<K>(                                   \
+      TileCfg, const K *, const uint32_t *, int64_t, const K *,                \
+      const uint32_t *, int64_t, K *, uint32_t *, const int64_t *, hipStream_t);
+MP_INSTANTIATE(uint32_t)
+MP_INSTANTIATE(int32_t)
+MP_INSTANTIATE(uint64_t)
+MP_INSTANTIATE(float)
+#undef MP_INSTANTIATE
+
+}  // namespace mp

@@ -1,0 +1,91 @@
+// Optional per-kernel timing with HIP events recorded on the launch stream.
+#include <atomic>
+#include <mutex>
+#include <string.h>
+#include <string>
+#include <vector>
+
+#include "mp_internal.h"
+
+namespace mp {
+namespace {
+
+struct Record {
+  std::string name;
+  hipEvent_t start, stop;
+};
+
+std::atomic<bool> g_on{false};
+std::mutex g_mu;
+std::vector<Record> g_records;
+
+void drop_all() {
+  for (auto &r : g_records) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  g_records.clear();
+}
+
+}  // namespace
+
+KernelTimer::KernelTimer(const char *name, hipStream_t s) : name_(name), s_(s) {
+  if (!g_on.load(std::memory_order_relaxed)) return;
+  if (hipEventCreate(&start_) != hipSuccess) {
+    start_ = nullptr;
+    return;
+  }
+  if (hipEventRecord(start_, s_) != hipSuccess) {
+    (void)hipEventDestroy(start_);
+    start_ = nullptr;
+  }
+}
+
+KernelTimer::~KernelTimer() {
+  if (!start_) return;
+  hipEvent_t stop = nullptr;
+  if (hipEventCreate(&stop) != hipSuccess || hipEventRecord(stop, s_) != hipSuccess) {
+    (void)hipEventDestroy(start_);
+    if (stop) (void)hipEventDestroy(stop);
+    return;
+  }
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_records.push_back(Record{name_, start_, stop});
+}
+
+}  // namespace mp
+
+using namespace mp;
+
+extern "C" {
+
+mp_status mp_timing_enable(int on) {
+  g_on.store(on != 0);
+  return MP_OK;
+}
+
+mp_status mp_timing_reset(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  drop_all();
+  return MP_OK;
+}
+
+mp_status mp_timing_query(const char *name, double *total_ms, int64_t *launches) {
+  if (!name || !total_ms || !launches) return MP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  double sum = 0.0;
+  int64_t cnt = 0;
+  for (auto &r : g_records) {
+    if (r.name != name) continue;
+    if (hipEventSynchronize(r.stop) != hipSuccess) return MP_ERR_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return MP_ERR_HIP;
+    sum += ms;
+    ++cnt;
+  }
+  *total_ms = sum;
+  *launches = cnt;
+  return MP_OK;
+}
+
+}  // extern "C"

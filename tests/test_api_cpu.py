@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI that need no GPU.
+
+The library must load and export every entry point declared in
+include/*.h, and every argument error must be reported before any device
+work (fake device pointers are never dereferenced on these paths).
+"""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1406_2628_amd", "libmergepath.so")
+
+MP_NONE, MP_U32, MP_I32, MP_U64, MP_F32 = 0, 1, 2, 3, 4
+OK, INVALID, UNSUPPORTED, OVERLAP, WORKSPACE = 0, -1, -2, -3, -4
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(mp_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    import paper_1406_2628_amd as mp
+    return mp.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for required in ["mp_partition", "mp_merge", "mp_merge_kv", "mp_sort", "mp_merge_batched"]:
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def P(x):
+    return ctypes.c_void_p(x)
+
+
+def test_merge_argument_errors(L):
+    a, b, s = P(0x10000), P(0x20000), P(0x30000)
+    assert L.mp_merge(99, a, 10, b, 10, s, None) == UNSUPPORTED
+    assert L.mp_merge(MP_U32, a, -1, b, 10, s, None) == INVALID
+    assert L.mp_merge(MP_U32, None, 10, b, 10, s, None) == INVALID
+    assert L.mp_merge(MP_U32, a, 10, b, 10, None, None) == INVALID
+    assert L.mp_merge(MP_U32, P(0x10001), 10, b, 10, s, None) == INVALID   # misaligned
+    assert L.mp_merge(MP_U32, a, 16, b, 16, P(0x10000 + 32), None) == OVERLAP
+    assert L.mp_merge(MP_U32, a, 16, b, 16, P(0x20000 - 64), None) == OVERLAP
+    assert b"overlap" in L.mp_last_error()
+    assert L.mp_merge(MP_U32, None, 0, None, 0, None, None) == OK          # empty no-op
+    assert L.mp_merge(MP_U64, a, 1 << 62, b, 1 << 62, s, None) in (INVALID, OVERLAP)
+
+
+def test_merge_kv_argument_errors(L):
+    ak, av, bk, bv, sk, sv = (P(x) for x in (0x10000, 0x20000, 0x30000, 0x40000, 0x50000, 0x60000))
+    assert L.mp_merge_kv(MP_U32, MP_NONE, ak, av, 4, bk, bv, 4, sk, sv, None) == INVALID
+    assert L.mp_merge_kv(MP_U32, MP_U64, ak, av, 4, bk, bv, 4, sk, sv, None) == UNSUPPORTED
+    assert L.mp_merge_kv(MP_U32, MP_U32, ak, None, 4, bk, bv, 4, sk, sv, None) == INVALID
+    assert L.mp_merge_kv(MP_U32, MP_U32, ak, av, 4, bk, bv, 4, sk, P(0x50000 + 16), None) == OVERLAP
+    assert L.mp_merge_kv(MP_U32, MP_U32, ak, av, 4, bk, bv, 4, sk, P(0x20000), None) == OVERLAP
+
+
+def test_partition_argument_errors(L):
+    a, b, d, o = P(0x10000), P(0x20000), P(0x30000), P(0x40000)
+    assert L.mp_partition(0, a, 4, b, 4, d, 4, o, None) == UNSUPPORTED
+    assert L.mp_partition(MP_F32, a, 4, b, 4, d, -3, o, None) == INVALID
+    assert L.mp_partition(MP_F32, a, 4, b, 4, d, 4, None, None) == INVALID
+    assert L.mp_partition(MP_F32, a, 4, b, 4, d, 4, P(0x30000 + 8), None) == OVERLAP
+    assert L.mp_partition(MP_F32, a, 4, b, 4, d, 0, o, None) == OK

@@ -1,0 +1,124 @@
+"""GPU parity of mp_partition, mp_merge and mp_merge_kv against the oracle (bit-exact)."""
+import numpy as np
+import pytest
+
+import mp_inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [gen.U32, gen.I32, gen.U64, gen.F32]
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1406_2628_amd as mp
+    mp.lib()
+    return mp
+
+
+def _cases():
+    # (na, nb) spanning several tiles, ragged tails, empties and skewed lengths
+    return [(0, 0), (0, 5), (7, 0), (1, 1), (1, 4096), (4096, 1), (4095, 4097),
+            (100_003, 77_777), (3, 250_000), (250_000, 3), (1 << 17, 1 << 17)]
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("na,nb", _cases())
+def test_merge_uniform(mp, orc, dt, na, nb):
+    from gpu_util import dev, host, first_mismatch
+    A, B = gen.uniform_pair(na, nb, 1000 + na + 7 * nb, dt)
+    got = host(mp.merge(dev(A), dev(B)))
+    want = orc.merge(A, B)
+    assert first_mismatch(got, want) is None, first_mismatch(got, want)
+
+
+@pytest.mark.parametrize("kind", ["dups", "disjoint", "disjoint_rev", "all_equal"])
+def test_merge_structured(mp, orc, kind):
+    from gpu_util import dev, host, first_mismatch
+    na, nb = 300_001, 200_017
+    if kind == "dups":
+        A, B = gen.dups_pair(na, nb, 22)
+    elif kind == "disjoint":
+        A, B = gen.disjoint_pair(na, nb, 23)
+    elif kind == "disjoint_rev":
+        B, A = gen.disjoint_pair(nb, na, 23)
+    else:
+        A, B = np.full(na, 7, np.uint32), np.full(nb, 7, np.uint32)
+    got = host(mp.merge(dev(A), dev(B)))
+    assert first_mismatch(got, orc.merge(A, B)) is None
+
+
+def test_merge_config1(mp, orc):
+    """|A| = |B| = 2^20 uniform u32 keys (seed 1)."""
+    from gpu_util import dev, host, first_mismatch
+    A, B = gen.uniform_pair(1 << 20, 1 << 20, 1)
+    got = host(mp.merge(dev(A), dev(B)))
+    assert first_mismatch(got, orc.merge(A, B)) is None
+
+
+def test_merge_extreme_keys(mp, orc):
+    from gpu_util import dev, host, first_mismatch
+    g = np.random.default_rng(5)
+    for dt, lo, hi in [(np.uint32, 0, 2**32 - 1), (np.int32, -2**31, 2**31 - 1),
+                       (np.uint64, 0, 2**64 - 1)]:
+        A = np.sort(g.choice(np.array([lo, hi, lo + 1, hi - 1], dtype=dt), 10_000))
+        B = np.sort(g.choice(np.array([lo, hi], dtype=dt), 7_000))
+        got = host(mp.merge(dev(A), dev(B)))
+        assert first_mismatch(got, orc.merge(A, B)) is None
+    f = np.finfo(np.float32).max
+    A = np.sort(g.choice(np.array([-f, -0.0, 0.0, f], dtype=np.float32), 10_000))
+    B = np.sort(g.choice(np.array([-f, 0.0, -0.0, f], dtype=np.float32), 9_000))
+    got = host(mp.merge(dev(A), dev(B)))
+    assert first_mismatch(got, orc.merge(A, B)) is None
+
+
+def test_merge_f32_mixture_signed_zeros(mp, orc):
+    from gpu_util import dev, host, first_mismatch
+    A, B = gen.f32_mixture_pair(200_000, 150_000, 51)
+    assert np.any(np.signbit(A) & (A == 0))
+    got = host(mp.merge(dev(A), dev(B)))
+    assert first_mismatch(got, orc.merge(A, B)) is None
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_partition(mp, orc, dt):
+    from gpu_util import dev, host
+    A, B = gen.uniform_pair(50_000, 30_001, 3, dt)
+    n = len(A) + len(B)
+    g = np.random.default_rng(0)
+    diag = np.concatenate([[0, n, 1, n - 1], g.integers(0, n + 1, 5000)]).astype(np.int64)
+    got = host(mp.partition(dev(A), dev(B), dev(diag)))
+    assert np.array_equal(got, orc.partition(A, B, diag))
+
+
+def test_partition_dups_and_skew(mp, orc):
+    from gpu_util import dev, host
+    for (na, nb) in [(1, 100_000), (100_000, 1), (0, 10), (10, 0)]:
+        A, B = gen.dups_pair(na, nb, 9, hi=16)
+        n = na + nb
+        diag = np.arange(0, n + 1, max(1, n // 997), dtype=np.int64)
+        got = host(mp.partition(dev(A), dev(B), dev(diag)))
+        assert np.array_equal(got, orc.partition(A, B, diag))
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("kind", ["uniform", "dups", "disjoint"])
+def test_merge_kv(mp, orc, dt, kind):
+    from gpu_util import dev, host, first_mismatch
+    na, nb = 123_457, 98_765
+    if kind == "uniform":
+        A, B = gen.uniform_pair(na, nb, 21, dt)
+    elif kind == "dups":
+        A, B = gen.dups_pair(na, nb, 22)
+        A, B = A.astype(gen.NP_DTYPE[dt]), B.astype(gen.NP_DTYPE[dt])
+    else:
+        A, B = gen.disjoint_pair(na, nb, 23)
+        A, B = A.astype(gen.NP_DTYPE[dt]), B.astype(gen.NP_DTYPE[dt])
+    va, vb = gen.index_payload(na, nb)
+    gk, gv = mp.merge_kv(dev(A), dev(va), dev(B), dev(vb))
+    wk, wv = orc.merge_kv(A, va, B, vb)
+    assert first_mismatch(host(gk), wk) is None
+    assert first_mismatch(host(gv), wv) is None
