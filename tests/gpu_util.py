@@ -24,10 +24,15 @@ def same_bits(x: np.ndarray, y: np.ndarray) -> bool:
 
 
 def first_mismatch(x: np.ndarray, y: np.ndarray):
-    xb = x.view(np.uint8).reshape(len(x), -1) if len(x) else x
-    yb = y.view(np.uint8).reshape(len(y), -1) if len(y) else y
+    """None if x and y hold the same bits, else a description of the first difference."""
+    if x.dtype != y.dtype:
+        return f"dtype {x.dtype} != {y.dtype}"
     if len(x) != len(y):
         return f"length {len(x)} != {len(y)}"
+    if len(x) == 0:
+        return None
+    xb = np.ascontiguousarray(x).view(np.uint8).reshape(len(x), -1)
+    yb = np.ascontiguousarray(y).view(np.uint8).reshape(len(y), -1)
     bad = np.nonzero(np.any(xb != yb, axis=1))[0]
     if len(bad) == 0:
         return None
