@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=28, help="log2 of |A| = |B|")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time only the reference copy of the same byte count")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -91,21 +93,32 @@ def main():
     dS = torch.empty(na + nb, dtype=torch.uint32, device="cuda")
     torch.cuda.synchronize()
 
+    n_out = na + nb
+    alg_bytes = n_out * 4 * 2   # every input key read once, every output key written once
+
+    if args.copy_probe:
+        # Reference copy of the same byte count (counter calibration, copy ceiling).
+        del dA, dB
+        src = torch.empty(n_out * 4, dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        ms = time_steps(lambda: mp.copy(src, dst), args.steps, args.warmup)
+        print(json.dumps({"probe": "copy", "bytes_moved": 2 * src.numel(), "ms": round(ms, 4),
+                          "GBs": round(2 * src.numel() / ms / 1e6, 1)}), flush=True)
+        return
+
     log("bench: timing mp_merge")
     step = lambda: mp.merge(dA, dB, out=dS)  # noqa: E731
     mp.timing_enable(False)
     ms = time_steps(step, args.steps, args.warmup)
-    # per-kernel durations over a second timed region, events on the launch stream
+    # per-kernel durations over a second timed region: HIP events recorded by
+    # the library on the launch stream around each kernel
     mp.timing_enable(True)
     time_steps(step, args.steps, 0)
-    k_ms, k_n = mp.timing_query("merge_tiles")
-    p_ms, p_n = mp.timing_query("tile_partition")
+    k_ms, k_n = mp.timing_query("merge_stream")
     mp.timing_enable(False)
     kern_ms = k_ms / max(1, k_n)
-    part_ms = p_ms / max(1, p_n)
 
-    n_out = na + nb
-    alg_bytes = n_out * 4 * 2   # every input key read once, every output key written once
     value = n_out / (ms * 1e-3) / 1e9
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
 
@@ -125,10 +138,10 @@ def main():
         "config": {"workload": f"merge u32 2^{args.log2n}+2^{args.log2n} uniform keys, seed {seed}",
                    "na": na, "nb": nb},
         "hbm_frac_step": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": {"bound": "hbm", "kernel": "merge_tile_kernel",
+        "roofline": {"bound": "hbm", "kernel": "merge_stream_kernel",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel_ms": round(kern_ms, 4), "partition_ms": round(part_ms, 4)},
+                     "kernel_ms": round(kern_ms, 4)},
     }
 
     if not args.no_verify or not args.no_cpu_baseline:

@@ -144,6 +144,48 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
                   void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Kernel variant selection (used by the autotuner and by tests that compare
+ * variants).  Applies to later calls of the named operation on every thread;
+ * it must not be changed while another thread is inside a library call.
+ *   op    "merge" (mp_merge and mp_merge_kv), "batched" (mp_merge_batched),
+ *         "sort" (the merge rounds of mp_sort)
+ *   cfg   NULL restores the built-in choice; otherwise
+ *         mode: 1 = per-tile (one grid split search per output tile, then
+ *                   one workgroup per tile; Algorithm 1 with p = tiles),
+ *               2 = persistent (each workgroup finds one split and walks a
+ *                   contiguous run of tiles, finding each next split in
+ *                   on-chip memory; Algorithm 3, Theorem 17)
+ *         nt, vt: lanes per workgroup and outputs per lane (tile = nt*vt)
+ *         grid: workgroups of a persistent launch, 0 = one resident wave
+ *         margin: persistent mode only.  Each tile's input windows are
+ *               sized from the previous tile's consumption plus `margin`
+ *               keys per input, with an exact reload when the split leaves
+ *               them.  0 = built-in margin, < 0 = always load full windows
+ *               (n keys of each input per tile of n outputs).
+ * Returns MP_ERR_UNSUPPORTED for an (nt, vt) pair that is not compiled in.
+ */
+typedef struct {
+  int32_t mode;
+  int32_t nt;
+  int32_t vt;
+  int32_t grid;
+  int32_t margin;
+} mp_config;
+mp_status mp_set_config(const char *op, const mp_config *cfg);
+
+/*
+ * mp_copy -- plain streaming copy of n_bytes (multiple of 16) from src to
+ * dst (16-byte aligned device pointers, non-overlapping), with the 16-byte
+ * loads and nontemporal stores the merge kernels use.  A measurement
+ * reference for achievable HBM bandwidth and for calibrating hardware
+ * traffic counters; not part of the merge method.
+ *   unroll  16-byte loads in flight per lane: 1, 2, 4 or 8 (0 = 8)
+ *   grid    workgroups of 256 lanes (0 = 32 per compute unit)
+ */
+mp_status mp_copy(const void *src, void *dst, int64_t n_bytes, int32_t unroll,
+                  int32_t grid, void *stream);
+
+/*
  * Kernel timing (profiling aid, off by default).  While enabled, every kernel
  * the library launches is bracketed by two HIP events recorded on the launch
  * stream.  mp_timing_query synchronises on the recorded events and returns,

@@ -54,6 +54,8 @@ def _declare(L):
         "mp_merge_batched": ([i32, p, p, p, p, i64, i64, i64, p, p, sz, p], i32),
         "mp_sort_workspace_bytes": ([i32, i32, i64], sz),
         "mp_sort": ([i32, i32, p, p, i64, p, sz, p], i32),
+        "mp_set_config": ([ctypes.c_char_p, ctypes.c_void_p], i32),
+        "mp_copy": ([p, p, i64, i32, i32, p], i32),
         "mp_timing_enable": ([i32], i32),
         "mp_timing_reset": ([], i32),
         "mp_timing_query": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -63,6 +65,29 @@ def _declare(L):
         f = getattr(L, name)
         f.argtypes, f.restype = args, res
     return L
+
+
+class Config(ctypes.Structure):
+    """Kernel variant (mp_config): mode 1 = per-tile, 2 = persistent."""
+    _fields_ = [("mode", ctypes.c_int32), ("nt", ctypes.c_int32),
+                ("vt", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("margin", ctypes.c_int32)]
+
+
+def set_config(op: str, mode: int | None = None, nt: int = 256, vt: int = 16, grid: int = 0,
+               margin: int = 0):
+    """Select the kernel variant of ``op`` ('merge', 'batched', 'sort'); mode None resets."""
+    if mode is None:
+        _check(lib().mp_set_config(op.encode(), None))
+    else:
+        cfg = Config(mode, nt, vt, grid, margin)
+        _check(lib().mp_set_config(op.encode(), ctypes.cast(ctypes.byref(cfg), ctypes.c_void_p)))
+
+
+def copy(src: torch.Tensor, dst: torch.Tensor, unroll: int = 0, grid: int = 0):
+    """Reference streaming copy of src's bytes into dst (bandwidth probe)."""
+    n = src.numel() * src.element_size()
+    _check(lib().mp_copy(_ptr(src), _ptr(dst), n, unroll, grid, _stream(src.device)))
 
 
 def timing_enable(on: bool = True):

@@ -49,7 +49,43 @@ mp_status check_array(const void *p, int64_t n, size_t es, const char *name) {
   return MP_OK;
 }
 
+enum Op { kOpMerge = 0, kOpBatched = 1, kOpSort = 2, kNumOps = 3 };
+
+// Built-in variant per operation (chosen from measurements on MI355X).
+const mp_config kDefaultConfig[kNumOps] = {
+    {2, 256, 16, 0, 0},  // merge
+    {2, 256, 16, 0, 0},  // batched
+    {2, 256, 16, 0, 0},  // sort rounds
+};
+mp_config g_config[kNumOps] = {kDefaultConfig[0], kDefaultConfig[1], kDefaultConfig[2]};
+
+mp_config current_config(Op op) { return g_config[op]; }
+
+int op_index(const char *name) {
+  if (!name) return -1;
+  if (!strcmp(name, "merge")) return kOpMerge;
+  if (!strcmp(name, "batched")) return kOpBatched;
+  if (!strcmp(name, "sort")) return kOpSort;
+  return -1;
+}
+
 }  // namespace
+
+int device_cu_count() {
+  static std::mutex mu;
+  static std::vector<int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (cache[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
 
 void *device_scratch(size_t bytes, hipError_t *err) {
   struct Slot {
@@ -145,26 +181,41 @@ static mp_status merge_common(const char *fn, mp_dtype kt, mp_dtype vt,
   }
   if (n == 0) return MP_OK;
 
-  const TileCfg cfg = default_tile_cfg(es, kv);
-  const int64_t T = (int64_t)cfg.nt * cfg.vt;
-  const int64_t n_tiles = (n + T - 1) / T;
-  hipError_t e = hipSuccess;
-  int64_t *splits = (int64_t *)device_scratch((size_t)(n_tiles + 1) * 8, &e);
-  if (!splits) return hip_fail(e, "workspace allocation");
   hipStream_t s = (hipStream_t)stream;
-  dispatch_key(kt, [&](auto k) {
-    using K = decltype(k);
-    {
-      KernelTimer timer("tile_partition", s);
-      e = launch_partition<K>((const K *)Ak, na, (const K *)Bk, nb, nullptr, T,
-                              n_tiles + 1, splits, s);
-    }
-    if (e != hipSuccess) return;
-    KernelTimer timer("merge_tiles", s);
-    e = launch_merge_tiles<K>(cfg, (const K *)Ak, (const uint32_t *)Av, na,
-                              (const K *)Bk, (const uint32_t *)Bv, nb, (K *)Sk,
-                              kv ? (uint32_t *)Sv : nullptr, splits, s);
-  });
+  const mp_config cfg = current_config(kOpMerge);
+  hipError_t e = hipSuccess;
+  if (cfg.mode == 1) {
+    const TileCfg tc{cfg.nt, cfg.vt};
+    const int64_t T = (int64_t)tc.nt * tc.vt;
+    const int64_t n_tiles = (n + T - 1) / T;
+    int64_t *splits = (int64_t *)device_scratch((size_t)(n_tiles + 1) * 8, &e);
+    if (!splits) return hip_fail(e, "workspace allocation");
+    dispatch_key(kt, [&](auto k) {
+      using K = decltype(k);
+      {
+        KernelTimer timer("tile_partition", s);
+        e = launch_partition<K>((const K *)Ak, na, (const K *)Bk, nb, nullptr, T,
+                                n_tiles + 1, splits, s);
+      }
+      if (e != hipSuccess) return;
+      KernelTimer timer("merge_tiles", s);
+      e = launch_merge_tiles<K>(tc, (const K *)Ak, (const uint32_t *)Av, na,
+                                (const K *)Bk, (const uint32_t *)Bv, nb, (K *)Sk,
+                                kv ? (uint32_t *)Sv : nullptr, splits, s);
+    });
+  } else {
+    const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
+    dispatch_key(kt, [&](auto k) {
+      using K = decltype(k);
+      KernelTimer timer("merge_stream", s);
+      e = launch_merge_stream<K>(sc, (const K *)Ak, (const uint32_t *)Av, na,
+                                 (const K *)Bk, (const uint32_t *)Bv, nb, (K *)Sk,
+                                 kv ? (uint32_t *)Sv : nullptr, s);
+    });
+  }
+  if (e == hipErrorNotSupported)
+    return fail(MP_ERR_UNSUPPORTED, "%s: configuration mode=%d nt=%d vt=%d not compiled in",
+                fn, cfg.mode, cfg.nt, cfg.vt);
   return e == hipSuccess ? MP_OK : hip_fail(e, "merge launch");
 }
 
@@ -179,6 +230,36 @@ mp_status mp_merge_kv(mp_dtype kt, mp_dtype vt, const void *Ak, const void *Av,
                       void *Sk, void *Sv, void *stream) {
   if (vt == MP_NONE) return fail(MP_ERR_INVALID_ARG, "mp_merge_kv: value dtype is MP_NONE");
   return merge_common("mp_merge_kv", kt, vt, Ak, Av, na, Bk, Bv, nb, Sk, Sv, stream);
+}
+
+mp_status mp_set_config(const char *op, const mp_config *cfg) {
+  const int i = op_index(op);
+  if (i < 0) return fail(MP_ERR_INVALID_ARG, "mp_set_config: unknown operation");
+  if (!cfg) {
+    g_config[i] = kDefaultConfig[i];
+    return MP_OK;
+  }
+  if ((cfg->mode != 1 && cfg->mode != 2) || cfg->nt <= 0 || cfg->vt <= 0 || cfg->grid < 0)
+    return fail(MP_ERR_INVALID_ARG, "mp_set_config: invalid configuration");
+  if (cfg->mode == 1 && i != kOpMerge)
+    return fail(MP_ERR_UNSUPPORTED, "mp_set_config: per-tile mode exists for merge only");
+  g_config[i] = *cfg;
+  return MP_OK;
+}
+
+mp_status mp_copy(const void *src, void *dst, int64_t n_bytes, int32_t unroll,
+                  int32_t grid, void *stream) {
+  if (n_bytes < 0 || n_bytes % 16) return fail(MP_ERR_INVALID_ARG, "mp_copy: n_bytes must be a non-negative multiple of 16");
+  if (n_bytes == 0) return MP_OK;
+  if (!src || !dst || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16))
+    return fail(MP_ERR_INVALID_ARG, "mp_copy: pointers must be non-NULL and 16-byte aligned");
+  if (overlaps(span(src, n_bytes, 1), span(dst, n_bytes, 1)))
+    return fail(MP_ERR_OVERLAP, "mp_copy: ranges overlap");
+  KernelTimer timer("copy", (hipStream_t)stream);
+  if (grid < 0) return fail(MP_ERR_INVALID_ARG, "mp_copy: negative grid");
+  hipError_t e = launch_copy(src, dst, n_bytes, unroll, grid, (hipStream_t)stream);
+  if (e == hipErrorNotSupported) return fail(MP_ERR_UNSUPPORTED, "mp_copy: unroll %d not provided", unroll);
+  return e == hipSuccess ? MP_OK : hip_fail(e, "mp_copy launch");
 }
 
 size_t mp_merge_batched_workspace_bytes(mp_dtype kt, int64_t n_pairs, int64_t total) {

@@ -16,6 +16,10 @@
 
 namespace mp {
 
+// 16-byte vector of four 32-bit words (native clang vector: usable with the
+// nontemporal load/store builtins and lowered to dwordx4 / b128 accesses).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // Bounds of the candidate a on diagonal d of an na x nb grid.
 template <typename I>
 __device__ __forceinline__ void diag_range(I d, I na, I nb, I &lo, I &hi) {
@@ -40,29 +44,29 @@ __device__ __forceinline__ I split_search(I d, I lo, I hi, GA ga, GB gb) {
 
 // Serial merge of VT outputs from a split, entirely in LDS (Lemma 1; the
 // loser of each compare stays in a register so each step reads one key).
-//   keys: LDS array holding the A window at [0, wa) and the B window at
-//         [wa, wa + wb); index wa + wb must be readable (one padding slot).
-//   ai, bi: LDS positions of the next A and B keys (bi already offset by wa).
-//   n_steps: how many outputs this lane produces (<= VT).
+//   keys: LDS array; A keys at positions [ai, a_end), B keys at [bi, b_end).
+//   ai, bi: LDS positions of the next A and B keys.
+// All VT steps run without guards: a lane whose run is shorter than VT keeps
+// stepping past it, and the caller discards those outputs.  Such extra steps
+// only read positions below max(a_end, b_end) + VT, which the caller keeps
+// inside the LDS array.
 // On return out[i] holds the keys and src[i] their LDS positions.
 template <typename K, int VT>
 __device__ __forceinline__ void serial_merge(const K *keys, int ai, int bi,
-                                             int a_end, int b_end, int n_steps,
+                                             int a_end, int b_end,
                                              K (&out)[VT], int (&src)[VT]) {
   K ka = keys[ai];
   K kb = keys[bi];
 #pragma unroll
   for (int i = 0; i < VT; ++i) {
-    if (i < n_steps) {
-      const bool take_b = (bi < b_end) && (ai >= a_end || kb < ka);
-      out[i] = take_b ? kb : ka;
-      src[i] = take_b ? bi : ai;
-      ai += take_b ? 0 : 1;
-      bi += take_b ? 1 : 0;
-      const K nxt = keys[take_b ? bi : ai];
-      ka = take_b ? ka : nxt;
-      kb = take_b ? nxt : kb;
-    }
+    const bool take_b = (bi < b_end) && (ai >= a_end || kb < ka);
+    out[i] = take_b ? kb : ka;
+    src[i] = take_b ? bi : ai;
+    ai += take_b ? 0 : 1;
+    bi += take_b ? 1 : 0;
+    const K nxt = keys[take_b ? bi : ai];
+    ka = take_b ? ka : nxt;
+    kb = take_b ? nxt : kb;
   }
 }
 

@@ -53,6 +53,27 @@ hipError_t launch_merge_tiles(TileCfg cfg, const K *A, const uint32_t *Av,
 
 TileCfg default_tile_cfg(size_t key_bytes, bool kv);
 
+// Persistent merge: nt lanes x vt outputs per tile, `grid` workgroups each
+// walking a contiguous run of tiles (0 = one full wave of resident groups).
+struct StreamCfg {
+  int nt;
+  int vt;
+  int grid;
+  int margin;  // speculative window margin: 0 = default, < 0 = full windows
+};
+
+template <typename K>
+hipError_t launch_merge_stream(StreamCfg cfg, const K *A, const uint32_t *Av,
+                               int64_t na, const K *B, const uint32_t *Bv,
+                               int64_t nb, K *S, uint32_t *Sv, hipStream_t s);
+
+// Plain 16-byte streaming copy (bandwidth reference).
+hipError_t launch_copy(const void *src, void *dst, int64_t n_bytes, int unroll,
+                       int grid, hipStream_t s);
+
+// Number of compute units of the current device (cached per device).
+int device_cu_count();
+
 // Brackets one kernel launch with HIP events on its stream while timing is
 // enabled (mp_timing_enable); does nothing otherwise.
 class KernelTimer {

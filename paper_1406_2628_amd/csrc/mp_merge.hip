@@ -50,7 +50,9 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(
     K *__restrict__ S, uint32_t *__restrict__ Sv,
     const int64_t *__restrict__ a_split) {
   constexpr int T = NT * VT;
-  __shared__ K keys[T + 1];
+  // slack of VT + 1 slots: the unguarded serial merge may read up to VT
+  // positions past the A window end (outputs discarded)
+  __shared__ K keys[T + VT + 1];
   __shared__ uint32_t vals[KV ? T : 1];
   const int tid = threadIdx.x;
   const int64_t tile = blockIdx.x;
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(
   const int steps = n - dl < VT ? n - dl : VT;
   K out[VT];
   int src[VT];
-  serial_merge<K, VT>(keys, a, wa + dl - a, wa, n, steps, out, src);
+  serial_merge<K, VT>(keys, a, wa + dl - a, wa, n, out, src);
   uint32_t ov[VT];
   if constexpr (KV) {
 #pragma unroll
@@ -150,7 +152,7 @@ hipError_t launch_merge_tiles(TileCfg cfg, const K *A, const uint32_t *Av,
   MP_TILE_CASE(256, 8)
   MP_TILE_CASE(128, 16)
 #undef MP_TILE_CASE
-  return hipErrorInvalidValue;
+  return hipErrorNotSupported;
 }
 
 #define MP_INSTANTIATE(K)                                                      \

@@ -1,0 +1,87 @@
+"""Every compiled kernel variant (the autotuner's candidates) gives the oracle's bits."""
+import numpy as np
+import pytest
+
+import mp_inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+MERGE_VARIANTS = [(1, 256, 16, 0), (1, 256, 15, 0), (1, 256, 8, 0), (1, 128, 16, 0),
+                  (2, 256, 16, 0), (2, 256, 8, 0), (2, 256, 12, 0), (2, 128, 16, 0),
+                  (2, 512, 8, 0), (2, 256, 16, 7), (2, 256, 16, 1)]
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1406_2628_amd as mp
+    mp.lib()
+    yield mp
+    mp.set_config("merge", None)
+
+
+@pytest.mark.parametrize("variant", MERGE_VARIANTS, ids=lambda v: "m%d_nt%d_vt%d_g%d" % v)
+def test_merge_variants(mp, orc, variant):
+    from gpu_util import dev, host, first_mismatch
+    mode, nt, vt, grid = variant
+    mp.set_config("merge", mode, nt, vt, grid)
+    try:
+        for (na, nb, seed) in [(100_003, 77_777, 1), (5, 60_000, 2), (60_000, 5, 3), (0, 1000, 4)]:
+            for dt in (gen.U32, gen.U64):
+                A, B = gen.uniform_pair(na, nb, seed, dt)
+                got = host(mp.merge(dev(A), dev(B)))
+                assert first_mismatch(got, orc.merge(A, B)) is None, (na, nb, dt)
+        A, B = gen.dups_pair(50_001, 70_003, 7, hi=100)
+        va, vb = gen.index_payload(len(A), len(B))
+        gk, gv = mp.merge_kv(dev(A), dev(va), dev(B), dev(vb))
+        wk, wv = orc.merge_kv(A, va, B, vb)
+        assert first_mismatch(host(gk), wk) is None
+        assert first_mismatch(host(gv), wv) is None
+    finally:
+        mp.set_config("merge", None)
+
+
+@pytest.mark.parametrize("margin", [-1, 1, 7, 0, 100000])
+@pytest.mark.parametrize("vt", [8, 12])
+def test_speculative_window_margins(mp, orc, margin, vt):
+    """Tiny margins force the exact full-window reload on almost every tile;
+    -1 disables speculation.  Every setting must give the oracle's bits."""
+    from gpu_util import dev, host, first_mismatch
+    mp.set_config("merge", 2, 256, vt, 0, margin)
+    try:
+        cases = [gen.uniform_pair(200_003, 150_001, 31), gen.dups_pair(180_001, 170_003, 32, hi=40),
+                 gen.disjoint_pair(120_000, 90_001, 33), gen.uniform_pair(7, 300_000, 34),
+                 gen.uniform_pair(300_000, 7, 35)]
+        for A, B in cases:
+            got = host(mp.merge(dev(A), dev(B)))
+            assert first_mismatch(got, orc.merge(A, B)) is None, (len(A), len(B), margin)
+        A, B = gen.dups_pair(100_001, 90_007, 36, hi=30)
+        va, vb = gen.index_payload(len(A), len(B))
+        gk, gv = mp.merge_kv(dev(A), dev(va), dev(B), dev(vb))
+        wk, wv = orc.merge_kv(A, va, B, vb)
+        assert first_mismatch(host(gk), wk) is None
+        assert first_mismatch(host(gv), wv) is None
+    finally:
+        mp.set_config("merge", None)
+
+
+def test_unaligned_views(mp, orc):
+    """Sub-array views whose base is not 16-byte aligned take the element-wise path."""
+    import torch
+    from gpu_util import dev, host, first_mismatch
+    A, B = gen.uniform_pair(30_001, 20_003, 9)
+    dA, dB = dev(A), dev(B)
+    out = torch.empty((len(A) - 1) + (len(B) - 3) + 1, dtype=torch.uint32, device="cuda")
+    got = host(mp.merge(dA[1:], dB[3:], out=out[1:]))
+    assert first_mismatch(got, orc.merge(A[1:], B[3:])) is None
+
+
+def test_copy_reference(mp):
+    import torch
+    x = torch.arange(1 << 20, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    mp.copy(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
