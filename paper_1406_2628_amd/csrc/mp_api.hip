@@ -264,27 +264,109 @@ mp_status mp_copy(const void *src, void *dst, int64_t n_bytes, int32_t unroll,
 
 size_t mp_merge_batched_workspace_bytes(mp_dtype kt, int64_t n_pairs, int64_t total) {
   (void)kt; (void)n_pairs; (void)total;
-  return 0;
+  return 0;  // the persistent kernel keeps its pair offsets in LDS
 }
 
 mp_status mp_merge_batched(mp_dtype kt, const void *A, const int64_t *a_off,
                            const void *B, const int64_t *b_off, int64_t n_pairs,
                            int64_t total_a, int64_t total_b, void *S, void *ws,
                            size_t ws_bytes, void *stream) {
-  (void)kt; (void)A; (void)a_off; (void)B; (void)b_off; (void)n_pairs;
-  (void)total_a; (void)total_b; (void)S; (void)ws; (void)ws_bytes; (void)stream;
-  return fail(MP_ERR_UNSUPPORTED, "mp_merge_batched: not built yet");
+  (void)ws; (void)ws_bytes;
+  const char *fn = "mp_merge_batched";
+  if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported key dtype %d", fn, (int)kt);
+  if (n_pairs < 0) return fail(MP_ERR_INVALID_ARG, "%s: negative pair count", fn);
+  const size_t es = dtype_size(kt);
+  mp_status st;
+  if ((st = check_array(A, total_a, es, "A")) != MP_OK) return st;
+  if ((st = check_array(B, total_b, es, "B")) != MP_OK) return st;
+  if (total_a > INT64_MAX - total_b) return fail(MP_ERR_INVALID_ARG, "%s: total overflows", fn);
+  const int64_t n = total_a + total_b;
+  if (n_pairs == 0 && n != 0)
+    return fail(MP_ERR_INVALID_ARG, "%s: keys given but no pairs", fn);
+  if ((st = check_array(a_off, n_pairs ? n_pairs + 1 : 0, 8, "a_off")) != MP_OK) return st;
+  if ((st = check_array(b_off, n_pairs ? n_pairs + 1 : 0, 8, "b_off")) != MP_OK) return st;
+  if ((st = check_array(S, n, es, "S")) != MP_OK) return st;
+  const Range rs = span(S, n, es);
+  if (overlaps(rs, span(A, total_a, es)) || overlaps(rs, span(B, total_b, es)) ||
+      overlaps(rs, span(a_off, n_pairs + 1, 8)) || overlaps(rs, span(b_off, n_pairs + 1, 8)))
+    return fail(MP_ERR_OVERLAP, "%s: output overlaps an input", fn);
+  if (n == 0) return MP_OK;
+  const mp_config cfg = current_config(kOpBatched);
+  const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  dispatch_key(kt, [&](auto k) {
+    using K = decltype(k);
+    KernelTimer timer("merge_batched", s);
+    e = launch_merge_batched<K>(sc, (const K *)A, a_off, (const K *)B, b_off, n_pairs,
+                                total_a, total_b, (K *)S, s);
+  });
+  if (e == hipErrorNotSupported)
+    return fail(MP_ERR_UNSUPPORTED, "%s: configuration nt=%d vt=%d not compiled in", fn, cfg.nt, cfg.vt);
+  return e == hipSuccess ? MP_OK : hip_fail(e, "mp_merge_batched launch");
+}
+
+// Workspace of mp_sort: a second buffer for keys (256-byte aligned) and, with
+// values, one for values; merge rounds ping-pong between it and the caller's
+// arrays.
+static size_t sort_ws_keys_bytes(size_t es, int64_t n) {
+  return ((size_t)n * es + 255) & ~(size_t)255;
 }
 
 size_t mp_sort_workspace_bytes(mp_dtype kt, mp_dtype vt, int64_t n) {
-  (void)kt; (void)vt; (void)n;
-  return 0;
+  const size_t es = dtype_size(kt);
+  if (es == 0 || n <= 0 || (vt != MP_NONE && !is_val32(vt))) return 0;
+  return sort_ws_keys_bytes(es, n) + (vt != MP_NONE ? (size_t)n * 4 : 0);
 }
 
 mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
                   void *ws, size_t ws_bytes, void *stream) {
-  (void)kt; (void)vt; (void)keys; (void)vals; (void)n; (void)ws; (void)ws_bytes; (void)stream;
-  return fail(MP_ERR_UNSUPPORTED, "mp_sort: not built yet");
+  const char *fn = "mp_sort";
+  if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported key dtype %d", fn, (int)kt);
+  const bool kv = vt != MP_NONE;
+  if (kv && !is_val32(vt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported value dtype %d", fn, (int)vt);
+  const size_t es = dtype_size(kt);
+  mp_status st;
+  if ((st = check_array(keys, n, es, "keys")) != MP_OK) return st;
+  if (kv && (st = check_array(vals, n, 4, "vals")) != MP_OK) return st;
+  if (!kv && vals) return fail(MP_ERR_INVALID_ARG, "%s: values given with value dtype MP_NONE", fn);
+  if (n <= 1) return MP_OK;
+  const size_t need = mp_sort_workspace_bytes(kt, vt, n);
+  if (!ws || ws_bytes < need)
+    return fail(MP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+  if ((uintptr_t)ws % 16) return fail(MP_ERR_INVALID_ARG, "%s: workspace not 16-byte aligned", fn);
+  const Range rw = span(ws, (int64_t)need, 1);
+  if (overlaps(rw, span(keys, n, es)) || (kv && overlaps(rw, span(vals, n, 4))) ||
+      (kv && overlaps(span(keys, n, es), span(vals, n, 4))))
+    return fail(MP_ERR_OVERLAP, "%s: workspace, keys and values must not overlap", fn);
+
+  const mp_config cfg = current_config(kOpSort);
+  const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  int rounds = 0;
+  for (int64_t w = kSortBlock; w < n; w <<= 1) ++rounds;
+  dispatch_key(kt, [&](auto k) {
+    using K = decltype(k);
+    K *kb[2] = {(K *)keys, (K *)ws};
+    uint32_t *vb[2] = {(uint32_t *)vals,
+                       kv ? (uint32_t *)((char *)ws + sort_ws_keys_bytes(es, n)) : nullptr};
+    // Choose where the sorted blocks land so that the last round writes the
+    // caller's arrays.
+    int cur = rounds % 2;
+    {
+      KernelTimer timer("blocksort", s);
+      e = launch_blocksort<K>((const K *)keys, (const uint32_t *)vals, kb[cur], vb[cur], n, s);
+    }
+    for (int lw = kSortBlockLog2; e == hipSuccess && ((int64_t)1 << lw) < n; ++lw) {
+      KernelTimer timer("sort_round", s);
+      e = launch_sort_round<K>(sc, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, lw, s);
+      cur ^= 1;
+    }
+  });
+  if (e == hipErrorNotSupported)
+    return fail(MP_ERR_UNSUPPORTED, "%s: configuration nt=%d vt=%d not compiled in", fn, cfg.nt, cfg.vt);
+  return e == hipSuccess ? MP_OK : hip_fail(e, "mp_sort launch");
 }
 
 }  // extern "C"

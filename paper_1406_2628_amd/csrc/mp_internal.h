@@ -67,6 +67,24 @@ hipError_t launch_merge_stream(StreamCfg cfg, const K *A, const uint32_t *Av,
                                int64_t na, const K *B, const uint32_t *Bv,
                                int64_t nb, K *S, uint32_t *Sv, hipStream_t s);
 
+// Batched merge of CSR-concatenated pairs (persistent, one launch).
+template <typename K>
+hipError_t launch_merge_batched(StreamCfg cfg, const K *A, const int64_t *a_off,
+                                const K *B, const int64_t *b_off, int64_t n_pairs,
+                                int64_t total_a, int64_t total_b, K *S, hipStream_t s);
+
+// One merge-sort round: runs of width 2^lw in X merged pairwise into Y.
+template <typename K>
+hipError_t launch_sort_round(StreamCfg cfg, const K *X, const uint32_t *Xv, K *Y,
+                             uint32_t *Yv, int64_t n, int lw, hipStream_t s);
+
+// Stable sort of each block of kSortBlock keys (in place allowed: in == out).
+constexpr int kSortBlockLog2 = 11;
+constexpr int kSortBlock = 1 << kSortBlockLog2;
+template <typename K>
+hipError_t launch_blocksort(const K *in, const uint32_t *vin, K *out, uint32_t *vout,
+                            int64_t n, hipStream_t s);
+
 // Plain 16-byte streaming copy (bandwidth reference).
 hipError_t launch_copy(const void *src, void *dst, int64_t n_bytes, int unroll,
                        int grid, hipStream_t s);

@@ -1,55 +1,83 @@
-// Persistent merge: each workgroup walks a contiguous run of output tiles.
+// Persistent merge over a global output index: one kernel for a single merge,
+// for batches of independent merges and for the rounds of merge sort.
 //
-// This is the segmented parallel merge of section 4 (Algorithm 3) mapped to a
-// GPU workgroup, with LDS in the role of the cache.  The workgroup keeps its
-// current split (a_cur, b_cur).  For a tile of n <= T outputs the path uses
-// at most n keys of A and n keys of B (Lemma 16), so windows of n keys each
-// always suffice; every lane then finds its split at local diagonal lane * VT
-// inside the windows (Theorem 17) and merges VT outputs serially, and the
-// tile's end split becomes the next tile's start.  Only the first split of
-// each workgroup is searched in global memory, by one wavefront probing 64
-// points of the diagonal per round (Theorem 14's search with a 65-way cut).
+// Each workgroup walks a contiguous run of output tiles (Corollary 7: equal
+// tiles balance the work).  This is the segmented parallel merge of section 4
+// (Algorithm 3) with LDS in the role of the cache: the workgroup keeps its
+// current split (a_cur, b_cur); a tile of n <= T outputs uses at most n keys
+// of A and n keys of B (Lemma 16), so windows of n keys each always suffice;
+// every lane finds its split at local diagonal lane * VT inside the windows
+// (Theorem 17) and merges VT outputs serially; the tile's end split becomes
+// the next tile's start.  Only the first split of each workgroup is searched
+// in global memory, by one wavefront probing 64 points per round (Theorem
+// 14's search with a 65-way cut).
+//
+// Pairs.  A batch is a list of independent pairs (A_k, B_k) laid end to end:
+// A' = A_0 A_1 ..., B' = B_0 B_1 ...; pair k's merge belongs at output offset
+// out(k) = a_off(k) + b_off(k) (Corollary 6 applied pair by pair).  Ordering
+// keys by (pair, key) makes A' and B' sorted and their merge the
+// concatenation of the pair merges, so the same Merge Path machinery applies
+// to the global output index.  The kernel realises the (pair, key) order
+// without storing pair ids: a split on global diagonal D lies inside pair
+// k = pair_of_out(D) (the last pair with out(k) <= D), and restricting the
+// search interval to that pair makes every probe compare two keys of the
+// same pair; a lane whose outputs cross a pair end switches to the next pair
+// there.  Three pair layouts share the kernel:
+//   kSingle    one pair (A, B): plain merge;
+//   kRuns      merge-sort round over X: pair k = (X[2wk, 2wk+w), X[2wk+w,
+//              2wk+2w)) clipped to n, left run as A (section 1, section 3);
+//   kExplicit  CSR offsets a_off[], b_off[] (batched merge), cached in LDS.
 //
 // Speculative windows.  Loading n keys of each input per tile would fetch
 // every key twice.  Instead the next tile's windows are sized from what the
-// current tile consumed (ca of A, cb of B) plus a margin M: la = ca + M and
-// lb = cb + M, capped by the full extents.  The end split found inside these
-// windows is exact unless it lands on a truncated window edge; in that case
-// the full windows are loaded and the tile is searched again, so the output
-// never depends on the prediction.  (Why the edge test suffices: every probe
-// of the search reads true keys, so the lower-bound search returns the true
-// split whenever it lies strictly inside the probed range; if it lies
-// outside, the search can only return a range end, and a range end that is a
-// truncated window edge is rejected.)
-//
-// The next tile's windows are fetched into registers right after the end
-// split is known, so their latency overlaps this tile's merge and stores.
+// current tile consumed plus a margin M, capped by the full extents.  The
+// end split found inside these windows is exact unless it lands on a
+// truncated window edge; then the full windows are loaded and the tile is
+// searched again, so the output never depends on the prediction.  (Every
+// probe reads true keys, so the lower-bound search returns the true split
+// whenever it lies strictly inside the probed range; otherwise it can only
+// return a range end, and a range end that is a truncated edge is rejected.)
+// The next tile's windows are fetched into registers as soon as the end
+// split is known, overlapping their latency with this tile's merge.
 #include "mp_device.h"
 #include "mp_internal.h"
 
 namespace mp {
 
-// Split on diagonal d by the 64 lanes of the calling wavefront; every lane
-// returns the same value.  Each round probes 64 interior points of the
-// candidate interval and keeps the gap where the predicate B[d-1-a] < A[a]
-// first turns true (it is monotone in a, Corollary 12).
+enum PairKind { kSingle = 0, kRuns = 1, kExplicit = 2 };
+
 template <typename K>
-__device__ int64_t wave_split_search(const K *__restrict__ A, int64_t na,
-                                     const K *__restrict__ B, int64_t nb,
-                                     int64_t d) {
+struct PairArgs {
+  const K *A, *B;          // kRuns: both are the source X
+  const uint32_t *Av, *Bv; // values (KV only)
+  K *S;
+  uint32_t *Sv;
+  int64_t NA, NB;          // lengths of A' and B'
+  int64_t n_tiles;
+  int margin;              // < 0: full windows
+  int lw;                  // kRuns: log2 of the run width
+  const int64_t *a_off, *b_off;  // kExplicit
+  int64_t n_pairs;
+};
+
+// Split on diagonal d of the grid A'[lo_a ...] x B' restricted to candidate
+// interval [lo, hi), found by the 64 lanes of the calling wavefront (every
+// lane returns the same value).  Each round probes 64 interior points and
+// keeps the gap where the predicate B'[d-1-a] < A'[a] first turns true (it
+// is monotone in a, Corollary 12).
+template <typename GA, typename GB>
+__device__ int64_t wave_split_search(int64_t d, int64_t lo, int64_t hi, GA ga, GB gb) {
   const int lane = threadIdx.x & 63;
-  int64_t lo, hi;
-  diag_range<int64_t>(d, na, nb, lo, hi);
   while (lo < hi) {
     const int64_t span = hi - lo;
     if (span <= 64) {
       const int64_t p = lo + lane;
-      const bool pred = lane < span && (B[d - 1 - p] < A[p]);
+      const bool pred = lane < span && (gb(d - 1 - p) < ga(p));
       const uint64_t m = __ballot(pred);
       return m ? lo + (int64_t)(__ffsll((long long)m) - 1) : hi;
     }
     const int64_t p = lo + ((int64_t)(lane + 1) * span) / 65;
-    const bool pred = B[d - 1 - p] < A[p];
+    const bool pred = gb(d - 1 - p) < ga(p);
     const uint64_t m = __ballot(pred);
     if (m == 0) {
       lo = lo + ((int64_t)64 * span) / 65 + 1;
@@ -98,12 +126,13 @@ __device__ __forceinline__ void store_chunk_lds(T *lds, const T (&v)[CH]) {
   }
 }
 
-// One tile's windows.  A keys from a_base (aligned to CH) sit at LDS 0, B keys
-// from b_base at LDS OB; the split (a_cur, b_cur) is at offsets sa, sb.
-//   wa, wb   full extents: keys of A and B this tile could use (<= n)
+// One tile's windows over A' and B'.  A' keys from a_base (aligned to CH) sit
+// at LDS 0, B' keys from b_base at LDS OB; the split (a_cur, b_cur) is at
+// offsets sa, sb.
+//   wa, wb   full extents: keys of A' and B' this tile could use (<= n)
 //   la, lb   loaded extents (la <= wa, lb <= wb)
 //   ca, cb   chunks covering [0, sa + la) and [0, sb + lb)
-//   fa, fb   chunks lying wholly inside their array (vector-loadable)
+//   fa, fb   chunks lying wholly inside A' / B' (vector-loadable)
 struct Window {
   int64_t a_base, b_base;
   int n, wa, wb, la, lb, sa, sb, ca, cb, fa, fb;
@@ -111,12 +140,12 @@ struct Window {
 
 template <int CH>
 __device__ __forceinline__ Window make_window(int64_t a_cur, int64_t b_cur,
-                                              int64_t na, int64_t nb, int n,
+                                              int64_t NA, int64_t NB, int n,
                                               int pa, int pb) {
   Window w;
   w.n = n;
-  w.wa = (int)(na - a_cur < n ? na - a_cur : n);
-  w.wb = (int)(nb - b_cur < n ? nb - b_cur : n);
+  w.wa = (int)(NA - a_cur < n ? NA - a_cur : n);
+  w.wb = (int)(NB - b_cur < n ? NB - b_cur : n);
   w.la = w.wa < pa ? w.wa : pa;
   w.lb = w.wb < pb ? w.wb : pb;
   w.a_base = a_cur & ~(int64_t)(CH - 1);
@@ -125,28 +154,14 @@ __device__ __forceinline__ Window make_window(int64_t a_cur, int64_t b_cur,
   w.sb = (int)(b_cur - w.b_base);
   w.ca = (w.sa + w.la + CH - 1) / CH;
   w.cb = (w.sb + w.lb + CH - 1) / CH;
-  const int64_t fa = (na - w.a_base) / CH, fb = (nb - w.b_base) / CH;
+  const int64_t fa = (NA - w.a_base) / CH, fb = (NB - w.b_base) / CH;
   w.fa = fa < w.ca ? (int)fa : w.ca;
   w.fb = fb < w.cb ? (int)fb : w.cb;
   return w;
 }
 
-// Global index, array and LDS position of chunk c of window w.
-template <int CH, int OB>
-__device__ __forceinline__ void chunk_place(const Window &w, int c, bool &from_b,
-                                            int64_t &g, int &pos, int &valid) {
-  from_b = c >= w.ca;
-  const int cc = from_b ? c - w.ca : c;
-  g = (from_b ? w.b_base : w.a_base) + (int64_t)cc * CH;
-  pos = (from_b ? OB : 0) + cc * CH;
-  valid = cc < (from_b ? w.fb : w.fa) ? CH : -1;  // -1: partial chunk
-}
-
-template <typename K, bool KV, int NT, int VT, bool VECTOR>
-__global__ __launch_bounds__(NT) void merge_stream_kernel(
-    const K *__restrict__ A, const uint32_t *__restrict__ Av, int64_t na,
-    const K *__restrict__ B, const uint32_t *__restrict__ Bv, int64_t nb,
-    K *__restrict__ S, uint32_t *__restrict__ Sv, int64_t n_tiles, int margin) {
+template <typename K, bool KV, int NT, int VT, int KIND, bool VECTOR>
+__global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   constexpr int T = NT * VT;
   constexpr int VEC = 16 / (int)sizeof(K);
   constexpr int CH = VECTOR ? VEC : 1;        // elements per staged chunk
@@ -157,36 +172,101 @@ __global__ __launch_bounds__(NT) void merge_stream_kernel(
   constexpr int MAX_MARGIN = T / 8;
   // chunks of speculative windows: (T + 2 * margin) keys plus alignment
   constexpr int PV = ((T + 2 * MAX_MARGIN) / CH + 4 + NT - 1) / NT;
+  constexpr int TP = KIND == kExplicit ? 128 : 1;  // cached pair offsets
   __shared__ __attribute__((aligned(16))) K keys[LDS_N];
   __shared__ __attribute__((aligned(16))) uint32_t vals[KV ? LDS_N : 1];
-  __shared__ int64_t s_split;
+  __shared__ int64_t t_a[TP + 1], t_b[TP + 1];  // a_off / b_off of pairs [tk, tk + TP]
+  __shared__ int64_t s_split, s_kf, s_kl, s_kf2, s_kl2, s_tk;
   __shared__ int s_end, s_valid;
 
+  const PairArgs<K> &P = args;
   const int tid = threadIdx.x;
-  const int64_t n_all = na + nb;
+  const int64_t NA = P.NA, NB = P.NB, N = NA + NB;
   // Balanced contiguous tile range of this workgroup (Corollary 7).
   const int64_t g = blockIdx.x, G = gridDim.x;
-  const int64_t t_begin = g * n_tiles / G;
-  const int64_t t_end = (g + 1) * n_tiles / G;
+  const int64_t t_begin = g * P.n_tiles / G;
+  const int64_t t_end = (g + 1) * P.n_tiles / G;
   if (t_begin >= t_end) return;
-  // margin < 0: always load full windows; otherwise at most T / 8
-  const bool speculate = margin >= 0;
-  const int M = margin > MAX_MARGIN ? MAX_MARGIN : margin;
+  const bool speculate = P.margin >= 0;
+  const int M = P.margin > MAX_MARGIN ? MAX_MARGIN : P.margin;
 
-  auto load_chunk = [&](const Window &w, int c, K (&kc)[CH], uint32_t (&vc)[CH]) {
-    bool from_b;
-    int64_t gi;
-    int pos, valid;
-    chunk_place<CH, OB>(w, c, from_b, gi, pos, valid);
-    const K *src = from_b ? B : A;
-    const uint32_t *vsrc = from_b ? Bv : Av;
-    if (valid > 0) {
-      load_chunk_full<K, CH>(src, gi, kc);
-      if constexpr (KV) load_chunk_full<uint32_t, CH>(vsrc, gi, vc);
+  // ---- addressing of A' and B' -------------------------------------------
+  auto a_addr = [&](int64_t i) -> int64_t {
+    if constexpr (KIND == kRuns) return i + ((i >> P.lw) << P.lw);
+    else return i;
+  };
+  auto b_addr = [&](int64_t j) -> int64_t {
+    if constexpr (KIND == kRuns) return ((int64_t)1 << P.lw) + j + ((j >> P.lw) << P.lw);
+    else return j;
+  };
+
+  // ---- pair structure ----------------------------------------------------
+  const int64_t n_pairs = KIND == kSingle   ? 1
+                          : KIND == kRuns   ? (N + ((int64_t)2 << P.lw) - 1) >> (P.lw + 1)
+                                            : P.n_pairs;
+  // kExplicit: first pair held in the LDS table (negative until it is loaded,
+  // which sends every lookup to global memory)
+  int64_t tk = -((int64_t)1 << 62);
+  auto aoff = [&](int64_t k) -> int64_t {
+    if constexpr (KIND == kSingle) return k == 0 ? 0 : NA;
+    else if constexpr (KIND == kRuns) { const int64_t v = k << P.lw; return v < NA ? v : NA; }
+    else return (uint64_t)(k - tk) <= (uint64_t)TP ? t_a[k - tk] : P.a_off[k];
+  };
+  auto boff = [&](int64_t k) -> int64_t {
+    if constexpr (KIND == kSingle) return k == 0 ? 0 : NB;
+    else if constexpr (KIND == kRuns) { const int64_t v = k << P.lw; return v < NB ? v : NB; }
+    else return (uint64_t)(k - tk) <= (uint64_t)TP ? t_b[k - tk] : P.b_off[k];
+  };
+  // Last pair k in [klo, khi] with out(k) <= D (out(klo) <= D is required).
+  auto pair_of_out = [&](int64_t D, int64_t klo, int64_t khi) -> int64_t {
+    if constexpr (KIND == kSingle) return 0;
+    else if constexpr (KIND == kRuns) {
+      const int64_t k = D >> (P.lw + 1);
+      return k < n_pairs - 1 ? k : n_pairs - 1;
     } else {
-      const int cnt = (int)((from_b ? nb : na) - gi);
-      load_chunk_part<K, CH>(src, gi, cnt, kc);
-      if constexpr (KV) load_chunk_part<uint32_t, CH>(vsrc, gi, cnt, vc);
+      // decide first whether the answer lies inside the cached table
+      const int64_t te = tk + TP;
+      if (tk >= 0 && klo >= tk && te <= khi) {
+        if (aoff(te) + boff(te) > D) khi = te - 1; else klo = te;
+      }
+      while (klo < khi) {
+        const int64_t mid = klo + ((khi - klo + 1) >> 1);
+        if (aoff(mid) + boff(mid) <= D) klo = mid; else khi = mid - 1;
+      }
+      return klo;
+    }
+  };
+  // Candidate interval (global A' index) of the split on global diagonal D
+  // inside pair k, intersected with a_cur <= a <= a_cur + la and
+  // b_cur <= D - a <= b_cur + lb.
+  auto pair_range = [&](int64_t D, int64_t k, int64_t a_cur, int64_t b_cur, int la,
+                        int lb, int64_t &lo, int64_t &hi) {
+    const int64_t ak = aoff(k), bk = boff(k), ak1 = aoff(k + 1), bk1 = boff(k + 1);
+    const int64_t dk = D - ak - bk;
+    lo = ak + (dk > bk1 - bk ? dk - (bk1 - bk) : 0);
+    hi = ak + (dk < ak1 - ak ? dk : ak1 - ak);
+    const int64_t lo2 = D - (b_cur + lb), hi2 = D - b_cur;
+    lo = lo > a_cur ? lo : a_cur;
+    lo = lo > lo2 ? lo : lo2;
+    hi = hi < a_cur + la ? hi : a_cur + la;
+    hi = hi < hi2 ? hi : hi2;
+  };
+
+  // ---- window staging ----------------------------------------------------
+  auto load_chunk = [&](const Window &w, int c, K (&kc)[CH], uint32_t (&vc)[CH]) {
+    const bool from_b = c >= w.ca;
+    const int cc = from_b ? c - w.ca : c;
+    const int64_t gi = (from_b ? w.b_base : w.a_base) + (int64_t)cc * CH;
+    const int64_t mi = from_b ? b_addr(gi) : a_addr(gi);
+    const K *src = from_b ? P.B : P.A;
+    const uint32_t *vsrc = from_b ? P.Bv : P.Av;
+    if (cc < (from_b ? w.fb : w.fa)) {
+      load_chunk_full<K, CH>(src, mi, kc);
+      if constexpr (KV) load_chunk_full<uint32_t, CH>(vsrc, mi, vc);
+    } else {
+      const int cnt = (int)((from_b ? NB : NA) - gi);
+      load_chunk_part<K, CH>(src, mi, cnt, kc);
+      if constexpr (KV) load_chunk_part<uint32_t, CH>(vsrc, mi, cnt, vc);
     }
   };
   auto put_chunk = [&](const Window &w, int c, const K (&kc)[CH], const uint32_t (&vc)[CH]) {
@@ -194,7 +274,6 @@ __global__ __launch_bounds__(NT) void merge_stream_kernel(
     store_chunk_lds<K, CH>(keys + pos, kc);
     if constexpr (KV) store_chunk_lds<uint32_t, CH>(vals + pos, vc);
   };
-  // Load every chunk of window w straight into LDS (prologue and fallback).
   auto load_now = [&](const Window &w) {
     for (int c = tid; c < w.ca + w.cb; c += NT) {
       K kc[CH];
@@ -203,7 +282,6 @@ __global__ __launch_bounds__(NT) void merge_stream_kernel(
       put_chunk(w, c, kc, vc);
     }
   };
-
   K pk[PV][CH];
   uint32_t pv[KV ? PV : 1][CH];
   auto prefetch = [&](const Window &w) {
@@ -226,76 +304,160 @@ __global__ __launch_bounds__(NT) void merge_stream_kernel(
       }
     }
   };
-  // Lower-bound split search on local diagonal dl inside the loaded windows.
-  auto local_search = [&](const Window &w, int dl) {
-    int lo, hi;
-    diag_range<int>(dl, w.la, w.lb, lo, hi);
-    const K *ka = keys + w.sa;
-    const K *kb = keys + OB + w.sb;
-    return split_search<int>(
-        dl, lo, hi, [&](int i) { return ka[i]; }, [&](int j) { return kb[j]; });
-  };
-  // End split of the tile plus the window-edge test (lane 0 only).
-  auto end_search = [&](const Window &w) {
-    int lo, hi;
-    diag_range<int>(w.n, w.la, w.lb, lo, hi);
-    const int r = local_search(w, w.n);
-    int tlo, thi;  // bounds over the full extents
-    diag_range<int>(w.n, w.wa, w.wb, tlo, thi);
-    s_end = r;
-    s_valid = lo <= hi && (r < hi || hi == thi) && (r > lo || lo == tlo);
+  auto load_table = [&](int64_t k0) {  // kExplicit: pairs [k0, k0 + TP]
+    for (int i = tid; i <= TP; i += NT) {
+      const int64_t k = k0 + i <= n_pairs ? k0 + i : n_pairs;
+      t_a[i] = P.a_off[k];
+      t_b[i] = P.b_off[k];
+    }
   };
 
+  // ---- searches inside the windows ---------------------------------------
+  int64_t a_cur = 0, b_cur = 0, d0 = 0;
+  // Window-local split on global diagonal D, pair searched in [kf, kl].
+  auto local_split = [&](const Window &w, int64_t D, int64_t kf, int64_t kl, int la, int lb,
+                         int64_t &k_out) -> int {
+    const int64_t k = pair_of_out(D, kf, kl);
+    k_out = k;
+    int64_t lo, hi;
+    pair_range(D, k, a_cur, b_cur, la, lb, lo, hi);
+    const K *ka = keys + w.sa;
+    const K *kb = keys + OB + w.sb;
+    const int dl = (int)(D - a_cur - b_cur);
+    int a = split_search<int>(dl, (int)(lo - a_cur), (int)(hi - a_cur),
+                              [&](int i) { return ka[i]; }, [&](int j) { return kb[j]; });
+    // An empty interval (only for a lane parked on the tile's last diagonal
+    // at a pair end, whose outputs are discarded) returns its low end; keep
+    // the position inside the windows.
+    a = a < la ? a : la;
+    a = a > dl - lb ? a : dl - lb;
+    return a > 0 ? a : 0;
+  };
+  // End split of the tile and the window-edge test; the next tile's pair
+  // range (lane 0 only).
+  auto end_search = [&](const Window &w, int64_t kf, int64_t kl) {
+    const int64_t D = d0 + w.n;
+    const int64_t k = pair_of_out(D, kl, n_pairs - 1);
+    int64_t lo, hi, tlo, thi, kk;
+    pair_range(D, k, a_cur, b_cur, w.la, w.lb, lo, hi);
+    pair_range(D, k, a_cur, b_cur, w.wa, w.wb, tlo, thi);
+    const int r = local_split(w, D, k, k, w.la, w.lb, kk);
+    const int64_t ra = a_cur + r;
+    s_end = r;
+    s_valid = lo <= hi && (ra < hi || hi == thi) && (ra > lo || lo == tlo);
+    s_kf2 = k;
+    const int64_t d1 = D + T < N ? D + T : N;
+    s_kl2 = d1 > D ? pair_of_out(d1 - 1, k, n_pairs - 1) : k;
+    (void)kf;
+  };
+
+  // ---- prologue: this workgroup's first split ----------------------------
+  d0 = t_begin * T;
   if (tid < 64) {
-    const int64_t d = t_begin * T < n_all ? t_begin * T : n_all;
-    const int64_t a = wave_split_search<K>(A, na, B, nb, d);
-    if (tid == 0) s_split = a;
+    const int64_t d = d0 < N ? d0 : N;
+    const int64_t k = pair_of_out(d, 0, n_pairs - 1);
+    // candidate interval of the split inside pair k
+    const int64_t ak = aoff(k), bk = boff(k), ak1 = aoff(k + 1), bk1 = boff(k + 1);
+    const int64_t dk = d - ak - bk;
+    int64_t lo = ak + (dk > bk1 - bk ? dk - (bk1 - bk) : 0);
+    int64_t hi = ak + (dk < ak1 - ak ? dk : ak1 - ak);
+    // no-ops for valid offsets; keep malformed ones inside the grid
+    int64_t glo, ghi;
+    diag_range<int64_t>(d, NA, NB, glo, ghi);
+    lo = lo < glo ? glo : (lo > ghi ? ghi : lo);
+    hi = hi < lo ? lo : (hi > ghi ? ghi : hi);
+    const int64_t a = wave_split_search(
+        d, lo, hi, [&](int64_t i) { return P.A[a_addr(i)]; },
+        [&](int64_t j) { return P.B[b_addr(j)]; });
+    if (tid == 0) {
+      s_split = a;
+      s_kf = k;
+      const int64_t d1 = d0 + T < N ? d0 + T : N;
+      s_kl = pair_of_out(d1 > d ? d1 - 1 : d, k, n_pairs - 1);
+    }
   }
   __syncthreads();
-  int64_t a_cur = s_split;
-  int64_t b_cur = t_begin * T - a_cur;
-  const int n0 = (int)(n_all - t_begin * T < T ? n_all - t_begin * T : T);
-  Window w = make_window<CH>(a_cur, b_cur, na, nb, n0, n0, n0);
+  a_cur = s_split;
+  b_cur = d0 - a_cur;
+  int64_t kf = s_kf, kl = s_kl;
+  if constexpr (KIND == kExplicit) {
+    tk = kf;
+    load_table(tk);
+  }
+  const int n0 = (int)(N - d0 < T ? N - d0 : T);
+  Window w = make_window<CH>(a_cur, b_cur, NA, NB, n0, n0, n0);
   load_now(w);
   __syncthreads();
 
   for (int64_t t = t_begin; t < t_end; ++t) {
-    const int64_t d0 = t * T;
+    d0 = t * T;
     const int n = w.n;
     const int dl = tid * VT < n ? tid * VT : n;
-    if (tid == 0) end_search(w);
-    int a_own = local_search(w, dl);
+    int64_t k_own;
+    if (tid == 0) end_search(w, kf, kl);
+    int a_own = local_split(w, d0 + dl, kf, kl, w.la, w.lb, k_own);
     __syncthreads();
     if (!s_valid) {
       // The split left the speculative windows: load the full ones (exact).
-      w = make_window<CH>(a_cur, b_cur, na, nb, n, n, n);
+      w = make_window<CH>(a_cur, b_cur, NA, NB, n, n, n);
       load_now(w);
       __syncthreads();
-      if (tid == 0) end_search(w);
-      a_own = local_search(w, dl);
+      if (tid == 0) end_search(w, kf, kl);
+      a_own = local_split(w, d0 + dl, kf, kl, w.la, w.lb, k_own);
       __syncthreads();
     }
     const int a_end = s_end;
     const int64_t a_next = a_cur + a_end, b_next = b_cur + (n - a_end);
+    const int64_t kf_next = s_kf2, kl_next = s_kl2;
 
     // Fetch the next tile's windows while this tile is merged.
     Window wn = w;
     const bool more = t + 1 < t_end;
     if (more) {
       const int64_t d1 = d0 + T;
-      const int n1 = (int)(n_all - d1 < T ? n_all - d1 : T);
+      const int n1 = (int)(N - d1 < T ? N - d1 : T);
       const int pa = speculate ? a_end + M : n1;
       const int pb = speculate ? (n - a_end) + M : n1;
-      wn = make_window<CH>(a_next, b_next, na, nb, n1, pa, pb);
-      // register prefetch holds speculative windows only; full windows are
-      // loaded at commit time
+      wn = make_window<CH>(a_next, b_next, NA, NB, n1, pa, pb);
       if (speculate) prefetch(wn);
     }
 
+    // Serial merge of this lane's VT outputs.
     K out[VT];
     int src[VT];
-    serial_merge<K, VT>(keys, w.sa + a_own, OB + w.sb + (dl - a_own), w.sa + w.la,
-                        OB + w.sb + w.lb, out, src);
+    {
+      const int64_t ak1 = aoff(k_own + 1), bk1 = boff(k_own + 1);
+      const int64_t D = d0 + dl;
+      auto clip_a = [&](int64_t e) { const int64_t l = e - a_cur; return w.sa + (int)(l < w.la ? l : w.la); };
+      auto clip_b = [&](int64_t e) { const int64_t l = e - b_cur; return OB + w.sb + (int)(l < w.lb ? l : w.lb); };
+      int ai = w.sa + a_own, bi = OB + w.sb + (dl - a_own);
+      if (KIND == kSingle || D + VT <= ak1 + bk1) {
+        serial_merge<K, VT>(keys, ai, bi, clip_a(ak1), clip_b(bk1), out, src);
+      } else {
+        // this lane's outputs cross the end of its pair
+        int64_t k = k_own, out_end = ak1 + bk1;
+        int a_e = clip_a(ak1), b_e = clip_b(bk1);
+        K ka = keys[ai], kb = keys[bi];
+#pragma unroll
+        for (int i = 0; i < VT; ++i) {
+          if (D + i == out_end && k + 1 < n_pairs) {
+            k = pair_of_out(D + i, k + 1, kl > k + 1 ? kl : k + 1);
+            const int64_t a2 = aoff(k + 1), b2 = boff(k + 1);
+            out_end = a2 + b2;
+            a_e = clip_a(a2);
+            b_e = clip_b(b2);
+          }
+          const bool take_b = (bi < b_e) && (ai >= a_e || kb < ka);
+          out[i] = take_b ? kb : ka;
+          src[i] = take_b ? bi : ai;
+          ai += take_b ? 0 : 1;
+          bi += take_b ? 1 : 0;
+          const K nxt = keys[take_b ? bi : ai];
+          ka = take_b ? ka : nxt;
+          kb = take_b ? nxt : kb;
+        }
+      }
+    }
     const int steps = n - dl < VT ? n - dl : VT;
     uint32_t ov[VT];
     if constexpr (KV) {
@@ -330,6 +492,8 @@ __global__ __launch_bounds__(NT) void merge_stream_kernel(
     }
     __syncthreads();
 
+    K *S = P.S;
+    uint32_t *Sv = P.Sv;
     if constexpr (VECTOR) {
       const int nvec = n / VEC;
       u32x4 *vdst = reinterpret_cast<u32x4 *>(S + d0);
@@ -354,78 +518,124 @@ __global__ __launch_bounds__(NT) void merge_stream_kernel(
     if (more) {
       if (speculate) commit(wn);
       else load_now(wn);
+      if constexpr (KIND == kExplicit) {
+        // slide the cached offsets when the next tile's pairs leave them
+        if (kl_next + 1 > tk + TP || kf_next < tk) {
+          tk = kf_next;
+          load_table(tk);
+        }
+      }
       __syncthreads();
     }
     a_cur = a_next;
     b_cur = b_next;
+    kf = kf_next;
+    kl = kl_next;
     w = wn;
   }
 }
 
-template <typename K, bool KV, int NT, int VT>
-static hipError_t launch_stream_impl(int grid, int margin, bool vec, const K *A,
-                                     const uint32_t *Av, int64_t na, const K *B,
-                                     const uint32_t *Bv, int64_t nb, K *S,
-                                     uint32_t *Sv, hipStream_t s) {
+template <typename K, bool KV, int NT, int VT, int KIND>
+static hipError_t launch_pairs_impl(int grid, bool vec, PairArgs<K> args, hipStream_t s) {
   constexpr int64_t T = NT * VT;
-  const int64_t n_tiles = (na + nb + T - 1) / T;
-  if (n_tiles == 0) return hipSuccess;
+  args.n_tiles = (args.NA + args.NB + T - 1) / T;
+  if (args.n_tiles == 0) return hipSuccess;
   if (grid <= 0) {
     // one full wave of resident workgroups
     static int per_cu = 0;
     if (per_cu == 0) {
       int occ = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-              &occ, merge_stream_kernel<K, KV, NT, VT, true>, NT, 0) != hipSuccess ||
+              &occ, merge_pairs_kernel<K, KV, NT, VT, KIND, true>, NT, 0) != hipSuccess ||
           occ <= 0)
         occ = 1;
       per_cu = occ;
     }
     grid = per_cu * device_cu_count();
   }
-  if (margin == 0) margin = 64 + (int)(T / 16);  // default prediction margin
-  const int64_t G = grid < n_tiles ? grid : n_tiles;
+  if (args.margin == 0) args.margin = 64 + (int)(T / 16);  // default prediction margin
+  const int64_t G = grid < args.n_tiles ? grid : args.n_tiles;
   if (vec)
-    hipLaunchKernelGGL((merge_stream_kernel<K, KV, NT, VT, true>), dim3((unsigned)G),
-                       dim3(NT), 0, s, A, Av, na, B, Bv, nb, S, Sv, n_tiles, margin);
+    hipLaunchKernelGGL((merge_pairs_kernel<K, KV, NT, VT, KIND, true>), dim3((unsigned)G),
+                       dim3(NT), 0, s, args);
   else
-    hipLaunchKernelGGL((merge_stream_kernel<K, KV, NT, VT, false>), dim3((unsigned)G),
-                       dim3(NT), 0, s, A, Av, na, B, Bv, nb, S, Sv, n_tiles, margin);
+    hipLaunchKernelGGL((merge_pairs_kernel<K, KV, NT, VT, KIND, false>), dim3((unsigned)G),
+                       dim3(NT), 0, s, args);
   return hipGetLastError();
 }
+
+template <typename K, int KIND>
+static hipError_t launch_pairs(StreamCfg cfg, bool vec, const PairArgs<K> &args,
+                               hipStream_t s) {
+  const bool kv = args.Sv != nullptr;
+#define MP_PAIRS_CASE(NT_, VT_)                                                    \
+  if (cfg.nt == NT_ && cfg.vt == VT_)                                              \
+    return kv ? launch_pairs_impl<K, true, NT_, VT_, KIND>(cfg.grid, vec, args, s) \
+              : launch_pairs_impl<K, false, NT_, VT_, KIND>(cfg.grid, vec, args, s);
+  MP_PAIRS_CASE(256, 16)
+  MP_PAIRS_CASE(256, 8)
+  MP_PAIRS_CASE(256, 12)
+  MP_PAIRS_CASE(128, 16)
+  MP_PAIRS_CASE(512, 8)
+#undef MP_PAIRS_CASE
+  return hipErrorNotSupported;
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p % 16) == 0; }
 
 template <typename K>
 hipError_t launch_merge_stream(StreamCfg cfg, const K *A, const uint32_t *Av,
                                int64_t na, const K *B, const uint32_t *Bv,
                                int64_t nb, K *S, uint32_t *Sv, hipStream_t s) {
+  PairArgs<K> a{};
+  a.A = A; a.B = B; a.Av = Av; a.Bv = Bv; a.S = S; a.Sv = Sv;
+  a.NA = na; a.NB = nb; a.margin = cfg.margin;
   const bool kv = Sv != nullptr;
-  // 16-byte paths need 16-byte aligned base pointers.
-  const bool vec = ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) &&
-                   ((uintptr_t)S % 16 == 0) &&
-                   (!kv || ((uintptr_t)Sv % 16 == 0 && (uintptr_t)Av % 16 == 0 &&
-                            (uintptr_t)Bv % 16 == 0));
-#define MP_STREAM_CASE(NT_, VT_)                                                 \
-  if (cfg.nt == NT_ && cfg.vt == VT_)                                            \
-    return kv ? launch_stream_impl<K, true, NT_, VT_>(cfg.grid, cfg.margin, vec, \
-                                                      A, Av, na, B, Bv, nb, S,   \
-                                                      Sv, s)                     \
-              : launch_stream_impl<K, false, NT_, VT_>(cfg.grid, cfg.margin, vec,\
-                                                       A, Av, na, B, Bv, nb, S,  \
-                                                       Sv, s);
-  MP_STREAM_CASE(256, 16)
-  MP_STREAM_CASE(256, 8)
-  MP_STREAM_CASE(256, 12)
-  MP_STREAM_CASE(128, 16)
-  MP_STREAM_CASE(512, 8)
-#undef MP_STREAM_CASE
-  return hipErrorNotSupported;
+  const bool vec = aligned16(A) && aligned16(B) && aligned16(S) &&
+                   (!kv || (aligned16(Sv) && aligned16(Av) && aligned16(Bv)));
+  return launch_pairs<K, kSingle>(cfg, vec, a, s);
 }
 
-#define MP_INSTANTIATE(K)                                                       \
-  template hipError_t launch_merge_stream<K>(StreamCfg, const K *,              \
-                                             const uint32_t *, int64_t,         \
-                                             const K *, const uint32_t *,       \
-                                             int64_t, K *, uint32_t *, hipStream_t);
+template <typename K>
+hipError_t launch_merge_batched(StreamCfg cfg, const K *A, const int64_t *a_off,
+                                const K *B, const int64_t *b_off, int64_t n_pairs,
+                                int64_t total_a, int64_t total_b, K *S, hipStream_t s) {
+  PairArgs<K> a{};
+  a.A = A; a.B = B; a.S = S;
+  a.NA = total_a; a.NB = total_b; a.margin = cfg.margin;
+  a.a_off = a_off; a.b_off = b_off; a.n_pairs = n_pairs;
+  const bool vec = aligned16(A) && aligned16(B) && aligned16(S);
+  return launch_pairs<K, kExplicit>(cfg, vec, a, s);
+}
+
+template <typename K>
+hipError_t launch_sort_round(StreamCfg cfg, const K *X, const uint32_t *Xv, K *Y,
+                             uint32_t *Yv, int64_t n, int lw, hipStream_t s) {
+  PairArgs<K> a{};
+  const int64_t w = (int64_t)1 << lw;
+  const int64_t q = n >> (lw + 1), r = n - (q << (lw + 1));
+  a.A = X; a.B = X; a.Av = Xv; a.Bv = Xv; a.S = Y; a.Sv = Yv;
+  a.NA = q * w + (r < w ? r : w);
+  a.NB = n - a.NA;
+  a.margin = cfg.margin;
+  a.lw = lw;
+  const bool kv = Yv != nullptr;
+  // run starts are multiples of w (>= 16 keys here), so CH-aligned chunks
+  // never straddle two runs
+  const bool vec = aligned16(X) && aligned16(Y) && (!kv || (aligned16(Xv) && aligned16(Yv))) &&
+                   w * (int64_t)sizeof(K) % 16 == 0;
+  return launch_pairs<K, kRuns>(cfg, vec, a, s);
+}
+
+#define MP_INSTANTIATE(K)                                                            \
+  template hipError_t launch_merge_stream<K>(StreamCfg, const K *, const uint32_t *, \
+                                             int64_t, const K *, const uint32_t *,   \
+                                             int64_t, K *, uint32_t *, hipStream_t); \
+  template hipError_t launch_merge_batched<K>(StreamCfg, const K *, const int64_t *, \
+                                              const K *, const int64_t *, int64_t,   \
+                                              int64_t, int64_t, K *, hipStream_t);   \
+  template hipError_t launch_sort_round<K>(StreamCfg, const K *, const uint32_t *,   \
+                                           K *, uint32_t *, int64_t, int, hipStream_t);
 MP_INSTANTIATE(uint32_t)
 MP_INSTANTIATE(int32_t)
 MP_INSTANTIATE(uint64_t)
