@@ -197,6 +197,15 @@ mp_status mp_timing_enable(int on);
 mp_status mp_timing_reset(void);
 mp_status mp_timing_query(const char *name, double *total_ms, int64_t *launches);
 
+/*
+ * Window statistics of the persistent merge kernels, collected while timing
+ * is enabled (device counters, zeroed by mp_timing_reset): the number of
+ * output tiles processed and how many of them left their predicted input
+ * windows and were searched again over full windows.  Synchronises with the
+ * device.  MP_ERR_INVALID_ARG for NULL outputs.
+ */
+mp_status mp_stats_query(int64_t *tiles, int64_t *reloads);
+
 #ifdef __cplusplus
 }
 #endif

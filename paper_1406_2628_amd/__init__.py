@@ -60,6 +60,7 @@ def _declare(L):
         "mp_timing_reset": ([], i32),
         "mp_timing_query": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_int64)], i32),
+        "mp_stats_query": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -100,6 +101,13 @@ def timing_query(name: str):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(lib().mp_timing_query(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def stats_query():
+    """(tiles, window reloads) of the persistent kernels since the last reset."""
+    t, r = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().mp_stats_query(ctypes.byref(t), ctypes.byref(r)))
+    return t.value, r.value
 
 
 def last_error() -> str:

@@ -243,6 +243,13 @@ mp_status mp_set_config(const char *op, const mp_config *cfg) {
     return fail(MP_ERR_INVALID_ARG, "mp_set_config: invalid configuration");
   if (cfg->mode == 1 && i != kOpMerge)
     return fail(MP_ERR_UNSUPPORTED, "mp_set_config: per-tile mode exists for merge only");
+  if (i == kOpSort) {
+    // merge rounds rely on tiles that divide every run pair (2w >= 2 blocks)
+    const int64_t t = (int64_t)cfg->nt * cfg->vt;
+    if ((t & (t - 1)) != 0 || t > 2 * kSortBlock)
+      return fail(MP_ERR_UNSUPPORTED, "mp_set_config: sort tiles must be a power of two <= %d",
+                  2 * kSortBlock);
+  }
   g_config[i] = *cfg;
   return MP_OK;
 }

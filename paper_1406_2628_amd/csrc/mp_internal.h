@@ -105,6 +105,10 @@ class KernelTimer {
   hipEvent_t start_ = nullptr;
 };
 
+// Device counters [tiles, window reloads] of the persistent kernels while
+// timing is enabled, nullptr otherwise.
+unsigned long long *stats_device_ptr();
+
 // Per-device scratch buffer owned by the library (grown on demand, kept until
 // the process ends).
 void *device_scratch(size_t bytes, hipError_t *err);

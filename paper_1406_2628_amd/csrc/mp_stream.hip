@@ -58,6 +58,7 @@ struct PairArgs {
   int lw;                  // kRuns: log2 of the run width
   const int64_t *a_off, *b_off;  // kExplicit
   int64_t n_pairs;
+  unsigned long long *stats;     // optional: [tiles, window reloads]
 };
 
 // Split on diagonal d of the grid A'[lo_a ...] x B' restricted to candidate
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   // B window end (<= OB + T + VEC - 1) plus VT slots read by the unguarded
   // serial merge past a window end
   constexpr int LDS_N = OB + T + VEC + VT + 1;
-  constexpr int MAX_MARGIN = T / 8;
+  constexpr int MAX_MARGIN = T / 16;
   // chunks of speculative windows: (T + 2 * margin) keys plus alignment
   constexpr int PV = ((T + 2 * MAX_MARGIN) / CH + 4 + NT - 1) / NT;
   constexpr int TP = KIND == kExplicit ? 128 : 1;  // cached pair offsets
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   __shared__ __attribute__((aligned(16))) uint32_t vals[KV ? LDS_N : 1];
   __shared__ int64_t t_a[TP + 1], t_b[TP + 1];  // a_off / b_off of pairs [tk, tk + TP]
   __shared__ int64_t s_split, s_kf, s_kl, s_kf2, s_kl2, s_tk;
-  __shared__ int s_end, s_valid;
+  __shared__ int s_end, s_valid, s_pa, s_pb;
 
   const PairArgs<K> &P = args;
   const int tid = threadIdx.x;
@@ -224,11 +225,14 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
       const int64_t k = D >> (P.lw + 1);
       return k < n_pairs - 1 ? k : n_pairs - 1;
     } else {
-      // decide first whether the answer lies inside the cached table
-      const int64_t te = tk + TP;
-      if (tk >= 0 && klo >= tk && te <= khi) {
-        if (aoff(te) + boff(te) > D) khi = te - 1; else klo = te;
+      // gallop from klo (the answer is usually klo or just past it), then
+      // finish with a binary search
+      int64_t step = 1;
+      while (klo + step <= khi && aoff(klo + step) + boff(klo + step) <= D) {
+        klo += step;
+        step <<= 1;
       }
+      khi = klo + step - 1 < khi ? klo + step - 1 : khi;
       while (klo < khi) {
         const int64_t mid = klo + ((khi - klo + 1) >> 1);
         if (aoff(mid) + boff(mid) <= D) klo = mid; else khi = mid - 1;
@@ -317,6 +321,18 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   // Window-local split on global diagonal D, pair searched in [kf, kl].
   auto local_split = [&](const Window &w, int64_t D, int64_t kf, int64_t kl, int la, int lb,
                          int64_t &k_out) -> int {
+    if constexpr (KIND == kSingle) {
+      // one pair: the window bounds are the whole interval
+      k_out = 0;
+      const int dl = (int)(D - a_cur - b_cur);
+      int lo, hi;
+      diag_range<int>(dl, la, lb, lo, hi);
+      const K *ka = keys + w.sa;
+      const K *kb = keys + OB + w.sb;
+      const int a = split_search<int>(
+          dl, lo, hi, [&](int i) { return ka[i]; }, [&](int j) { return kb[j]; });
+      return a < la ? a : la;
+    }
     const int64_t k = pair_of_out(D, kf, kl);
     k_out = k;
     int64_t lo, hi;
@@ -335,20 +351,50 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   };
   // End split of the tile and the window-edge test; the next tile's pair
   // range (lane 0 only).
-  auto end_search = [&](const Window &w, int64_t kf, int64_t kl) {
+  // Lane 0 searches the tile's end diagonal in step with the other lanes'
+  // own searches (its own split, at local diagonal 0, is known), then
+  // records it here: end split r inside pair k, the window-edge test, the
+  // next tile's pair range and the next windows' sizes.
+  auto end_record = [&](const Window &w, int64_t k, int r) {
     const int64_t D = d0 + w.n;
-    const int64_t k = pair_of_out(D, kl, n_pairs - 1);
-    int64_t lo, hi, tlo, thi, kk;
+    int64_t lo, hi, tlo, thi;
     pair_range(D, k, a_cur, b_cur, w.la, w.lb, lo, hi);
     pair_range(D, k, a_cur, b_cur, w.wa, w.wb, tlo, thi);
-    const int r = local_split(w, D, k, k, w.la, w.lb, kk);
     const int64_t ra = a_cur + r;
     s_end = r;
     s_valid = lo <= hi && (ra < hi || hi == thi) && (ra > lo || lo == tlo);
     s_kf2 = k;
     const int64_t d1 = D + T < N ? D + T : N;
     s_kl2 = d1 > D ? pair_of_out(d1 - 1, k, n_pairs - 1) : k;
-    (void)kf;
+    // Window sizes for the next tile: predict its end split, then add the
+    // margin.  Inside the same pair the path keeps this tile's A/B mix; a new
+    // pair starts from its own A fraction.  The pair's candidate interval
+    // caps both windows exactly.
+    if (d1 > D) {
+      const int64_t k1 = pair_of_out(d1, s_kl2, n_pairs - 1);
+      const int64_t ak = aoff(k1), bk = boff(k1), ak1 = aoff(k1 + 1), bk1 = boff(k1 + 1);
+      const int64_t dk = d1 - ak - bk;
+      const int64_t lo1 = ak + (dk > bk1 - bk ? dk - (bk1 - bk) : 0);
+      const int64_t hi1 = ak + (dk < ak1 - ak ? dk : ak1 - ak);
+      const int64_t a_nx = ra, b_nx = D - ra;
+      int64_t ap;
+      const int64_t ok = ak + bk;  // output offset where pair k1 starts
+      if (k1 == k && D - (ok > d0 ? ok : d0) >= T / 2) {
+        // keep the A/B mix pair k showed inside this tile
+        const int64_t from_d = ok > d0 ? ok : d0, from_a = ok > d0 ? ak : a_cur;
+        const int n1 = (int)(d1 - D);
+        ap = a_nx + (int64_t)((float)(ra - from_a) * (float)n1 / (float)(D - from_d));
+      } else {
+        const int64_t sk = (ak1 - ak) + (bk1 - bk);
+        ap = ak + (sk > 0 ? (int64_t)((double)dk * (double)(ak1 - ak) / (double)sk) : 0);
+      }
+      const int64_t alo = lo1 > a_nx ? lo1 : a_nx;
+      const int64_t ahi = hi1 < a_nx + (d1 - D) ? hi1 : a_nx + (d1 - D);
+      ap = ap < alo ? alo : (ap > ahi ? ahi : ap);
+      const int64_t pa = ap - a_nx + M, pb = (d1 - ap) - b_nx + M;
+      s_pa = (int)(pa < hi1 - a_nx ? pa : hi1 - a_nx);
+      s_pb = (int)(pb < (d1 - lo1) - b_nx ? pb : (d1 - lo1) - b_nx);
+    }
   };
 
   // ---- prologue: this workgroup's first split ----------------------------
@@ -389,23 +435,30 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   load_now(w);
   __syncthreads();
 
+  unsigned long long n_reload = 0;
   for (int64_t t = t_begin; t < t_end; ++t) {
     d0 = t * T;
     const int n = w.n;
     const int dl = tid * VT < n ? tid * VT : n;
-    int64_t k_own;
-    if (tid == 0) end_search(w, kf, kl);
-    int a_own = local_split(w, d0 + dl, kf, kl, w.la, w.lb, k_own);
+    // Lane 0's own split is the window start; it searches the end diagonal.
+    const int64_t dq = tid == 0 ? d0 + n : d0 + dl;
+    const int64_t kq_lo = tid == 0 ? kl : kf, kq_hi = tid == 0 ? n_pairs - 1 : kl;
+    int64_t k_q;
+    int r_q = local_split(w, dq, kq_lo, kq_hi, w.la, w.lb, k_q);
+    if (tid == 0) end_record(w, k_q, r_q);
     __syncthreads();
     if (!s_valid) {
       // The split left the speculative windows: load the full ones (exact).
+      ++n_reload;
       w = make_window<CH>(a_cur, b_cur, NA, NB, n, n, n);
       load_now(w);
       __syncthreads();
-      if (tid == 0) end_search(w, kf, kl);
-      a_own = local_split(w, d0 + dl, kf, kl, w.la, w.lb, k_own);
+      r_q = local_split(w, dq, kq_lo, kq_hi, w.la, w.lb, k_q);
+      if (tid == 0) end_record(w, k_q, r_q);
       __syncthreads();
     }
+    const int a_own = tid == 0 ? 0 : r_q;
+    const int64_t k_own = tid == 0 ? kf : k_q;
     const int a_end = s_end;
     const int64_t a_next = a_cur + a_end, b_next = b_cur + (n - a_end);
     const int64_t kf_next = s_kf2, kl_next = s_kl2;
@@ -416,8 +469,8 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     if (more) {
       const int64_t d1 = d0 + T;
       const int n1 = (int)(N - d1 < T ? N - d1 : T);
-      const int pa = speculate ? a_end + M : n1;
-      const int pb = speculate ? (n - a_end) + M : n1;
+      const int pa = speculate ? s_pa : n1;
+      const int pb = speculate ? s_pb : n1;
       wn = make_window<CH>(a_next, b_next, NA, NB, n1, pa, pb);
       if (speculate) prefetch(wn);
     }
@@ -431,19 +484,29 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
       auto clip_a = [&](int64_t e) { const int64_t l = e - a_cur; return w.sa + (int)(l < w.la ? l : w.la); };
       auto clip_b = [&](int64_t e) { const int64_t l = e - b_cur; return OB + w.sb + (int)(l < w.lb ? l : w.lb); };
       int ai = w.sa + a_own, bi = OB + w.sb + (dl - a_own);
-      if (KIND == kSingle || D + VT <= ak1 + bk1) {
+      // Run pairs span 2w >= 2 * 2048 outputs and start at multiples of 2w,
+      // and sort tiles are powers of two no larger than 4096 (the host
+      // enforces it), so a run pair never ends inside a tile.  Batches cross
+      // pair ends often: they always take the pair-tracking loop below.
+      if (KIND == kSingle || KIND == kRuns) {
         serial_merge<K, VT>(keys, ai, bi, clip_a(ak1), clip_b(bk1), out, src);
       } else {
         // this lane's outputs cross the end of its pair
-        int64_t k = k_own, out_end = ak1 + bk1;
+        // pair end as a tile-local output index (capped past this lane's run)
+        auto local_end = [&](int64_t e) {
+          const int64_t l = e - d0;
+          return (int)(l < dl + VT + 1 ? l : dl + VT + 1);
+        };
+        int64_t k = k_own;
+        int oe = local_end(ak1 + bk1);
         int a_e = clip_a(ak1), b_e = clip_b(bk1);
         K ka = keys[ai], kb = keys[bi];
 #pragma unroll
         for (int i = 0; i < VT; ++i) {
-          if (D + i == out_end && k + 1 < n_pairs) {
+          if (dl + i == oe && k + 1 < n_pairs) {
             k = pair_of_out(D + i, k + 1, kl > k + 1 ? kl : k + 1);
             const int64_t a2 = aoff(k + 1), b2 = boff(k + 1);
-            out_end = a2 + b2;
+            oe = local_end(a2 + b2);
             a_e = clip_a(a2);
             b_e = clip_b(b2);
           }
@@ -533,12 +596,17 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     kl = kl_next;
     w = wn;
   }
+  if (P.stats && tid == 0) {
+    atomicAdd(&P.stats[0], (unsigned long long)(t_end - t_begin));
+    atomicAdd(&P.stats[1], n_reload);
+  }
 }
 
 template <typename K, bool KV, int NT, int VT, int KIND>
 static hipError_t launch_pairs_impl(int grid, bool vec, PairArgs<K> args, hipStream_t s) {
   constexpr int64_t T = NT * VT;
   args.n_tiles = (args.NA + args.NB + T - 1) / T;
+  args.stats = stats_device_ptr();
   if (args.n_tiles == 0) return hipSuccess;
   if (grid <= 0) {
     // one full wave of resident workgroups
@@ -553,7 +621,10 @@ static hipError_t launch_pairs_impl(int grid, bool vec, PairArgs<K> args, hipStr
     }
     grid = per_cu * device_cu_count();
   }
-  if (args.margin == 0) args.margin = 64 + (int)(T / 16);  // default prediction margin
+  // default prediction margin: about four standard deviations of the change
+  // in the A/B mix between consecutive tiles for independent uniform keys
+  // (sqrt(T / 2)), plus slack
+  if (args.margin == 0) args.margin = 64 + (int)(T / 32);
   const int64_t G = grid < args.n_tiles ? grid : args.n_tiles;
   if (vec)
     hipLaunchKernelGGL((merge_pairs_kernel<K, KV, NT, VT, KIND, true>), dim3((unsigned)G),

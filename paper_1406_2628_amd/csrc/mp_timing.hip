@@ -18,6 +18,8 @@ struct Record {
 std::atomic<bool> g_on{false};
 std::mutex g_mu;
 std::vector<Record> g_records;
+unsigned long long *g_stats = nullptr;  // device: [tiles, window reloads]
+int g_stats_dev = -1;
 
 void drop_all() {
   for (auto &r : g_records) {
@@ -27,7 +29,26 @@ void drop_all() {
   g_records.clear();
 }
 
+// Zero the counters (allocating them on the current device on first use).
+hipError_t reset_stats() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (!g_stats || g_stats_dev != dev) {
+    if (g_stats) (void)hipFree(g_stats);
+    g_stats = nullptr;
+    e = hipMalloc(&g_stats, 2 * sizeof(unsigned long long));
+    if (e != hipSuccess) return e;
+    g_stats_dev = dev;
+  }
+  return hipMemset(g_stats, 0, 2 * sizeof(unsigned long long));
+}
+
 }  // namespace
+
+unsigned long long *stats_device_ptr() {
+  return g_on.load(std::memory_order_relaxed) ? g_stats : nullptr;
+}
 
 KernelTimer::KernelTimer(const char *name, hipStream_t s) : name_(name), s_(s) {
   if (!g_on.load(std::memory_order_relaxed)) return;
@@ -60,6 +81,8 @@ using namespace mp;
 extern "C" {
 
 mp_status mp_timing_enable(int on) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (on && !g_stats && reset_stats() != hipSuccess) return MP_ERR_HIP;
   g_on.store(on != 0);
   return MP_OK;
 }
@@ -67,6 +90,18 @@ mp_status mp_timing_enable(int on) {
 mp_status mp_timing_reset(void) {
   std::lock_guard<std::mutex> lock(g_mu);
   drop_all();
+  if (g_stats && reset_stats() != hipSuccess) return MP_ERR_HIP;
+  return MP_OK;
+}
+
+mp_status mp_stats_query(int64_t *tiles, int64_t *reloads) {
+  if (!tiles || !reloads) return MP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  unsigned long long h[2] = {0, 0};
+  if (g_stats && hipMemcpy(h, g_stats, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
+    return MP_ERR_HIP;
+  *tiles = (int64_t)h[0];
+  *reloads = (int64_t)h[1];
   return MP_OK;
 }
 

@@ -71,7 +71,13 @@ def test_sort_presorted_and_reversed(mp, orc):
         assert first_mismatch(got, orc.sort(keys)) is None
 
 
-@pytest.mark.parametrize("variant", [(2, 256, 8, 0, 0), (2, 256, 12, 0, 0), (2, 512, 8, 0, 0),
+def test_sort_rejects_tiles_that_do_not_divide_run_pairs(mp):
+    with pytest.raises(mp.MergePathError, match="UNSUPPORTED"):
+        mp.set_config("sort", 2, 256, 12)
+    mp.set_config("sort", None)
+
+
+@pytest.mark.parametrize("variant", [(2, 256, 8, 0, 0), (2, 512, 8, 0, 0), (2, 128, 16, 0, 0),
                                      (2, 256, 16, 0, -1), (2, 256, 16, 0, 1), (2, 128, 16, 3, 0)])
 def test_sort_round_variants(mp, orc, variant):
     from gpu_util import dev, host, first_mismatch
