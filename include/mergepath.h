@@ -144,6 +144,84 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
                   void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Learned split predictor.  Not part of the paper: a small FP32 MLP
+ * predicts where the Merge Path crosses a diagonal, and the exact search of
+ * Algorithm 2 then runs only in a window of +-w around the prediction.  A
+ * result on a window edge that is not a diagonal bound is checked against
+ * both conditions of Algorithm 2; if they fail, the full-range search runs.
+ * mp_partition_learned therefore always returns exactly what mp_partition
+ * returns; the model only changes how many probes that takes.
+ *
+ * Model: inputs x = [t, sin 2pi t, cos 2pi t, sin 4pi t, cos 4pi t][:F] with
+ * t = d / (na + nb); y = w2 . relu(W1 x + b1) + b2; the prediction is
+ * a_prior(d) + round(y * na), a_prior(d) = clamp(round(d * na / (na + nb))).
+ * Parameter vector (float32): [W1 (H x F row-major), b1 (H), w2 (H), b2].
+ * A handle owns its device memory (parameters, Adam moments, training
+ * buffers) and must not be used by two threads at once.
+ */
+typedef struct mp_lp_s *mp_lp;
+
+/* New model with `hidden` units (1..64) and `features` inputs (1, 3 or 5),
+   weights drawn from `seed`; window unset. */
+mp_status mp_lp_create(mp_lp *h, int hidden, int features, uint64_t seed);
+void mp_lp_destroy(mp_lp h);
+int mp_lp_num_params(mp_lp h);
+/* Number of inputs F and hidden units H of the model (HOST outputs). */
+mp_status mp_lp_shape(mp_lp h, int *features, int *hidden);
+/* Copy the n = mp_lp_num_params(h) parameters to / from HOST memory
+   (set also clears the Adam moments and step count). */
+mp_status mp_lp_get_params(mp_lp h, float *host, int n);
+mp_status mp_lp_set_params(mp_lp h, const float *host, int n);
+/* Search window half-width w (>= 0); mp_lp_calibrate sets it. */
+mp_status mp_lp_set_window(mp_lp h, int64_t window);
+int64_t mp_lp_window(mp_lp h); /* -1 when unset */
+
+/* Training examples for K stratified diagonals of one (A, B) set: the exact
+   splits from the plain search, features X (K x F, device float) and
+   targets r (K, device float) = (a* - a_prior) / na; diag and split (device
+   int64, may be NULL) receive the diagonals and exact splits. */
+mp_status mp_lp_examples(mp_lp h, mp_dtype kt, const void *A, int64_t na,
+                         const void *B, int64_t nb, int64_t K, uint64_t seed,
+                         float *X, float *r, int64_t *diag, int64_t *split,
+                         void *stream);
+/* y[k] = model(X[k]) for K rows of X (device). */
+mp_status mp_lp_forward(mp_lp h, const float *X, int64_t K, float *y, void *stream);
+/* Full-batch gradient of mean((y - r)^2) into grad (device, num_params
+   floats) and, if loss is not NULL, the loss (device float); reductions run
+   in a fixed order, so repeated calls give identical bits. */
+mp_status mp_lp_grad(mp_lp h, const float *X, const float *r, int64_t K,
+                     float *grad, float *loss, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. */
+mp_status mp_lp_adam_step(mp_lp h, const float *X, const float *r, int64_t K,
+                          float lr, void *stream);
+/* Train on n_sets (A_i, B_i) pairs: As/Bs are HOST arrays of device
+   pointers, nas/nbs HOST arrays of lengths; k_diag stratified diagonals per
+   set get exact splits from the plain search; then `epochs` full-batch Adam
+   steps with learning rate decaying from lr (cosine).  final_loss (HOST,
+   may be NULL) receives the last loss; this synchronises the stream. */
+mp_status mp_lp_train(mp_lp h, mp_dtype kt, const void *const *As,
+                      const int64_t *nas, const void *const *Bs,
+                      const int64_t *nbs, int n_sets, int64_t k_diag, int epochs,
+                      float lr, float *final_loss, void *stream);
+/* Set the window from a held-out set: the largest |prediction - split| over
+   n_diag stratified diagonals, plus a quarter, plus one.  max_err (HOST, may
+   be NULL) receives that largest error.  Synchronises the stream. */
+mp_status mp_lp_calibrate(mp_lp h, mp_dtype kt, const void *A, int64_t na,
+                          const void *B, int64_t nb, int64_t n_diag,
+                          int64_t *max_err, void *stream);
+/* As mp_partition (identical output), searching only the predicted window.
+   n_fallback (device uint64, may be NULL) is incremented once per diagonal
+   whose split fell outside its window.  MP_ERR_STATE if no window is set. */
+mp_status mp_partition_learned(mp_lp h, mp_dtype kt, const void *A, int64_t na,
+                               const void *B, int64_t nb, const int64_t *diag,
+                               int64_t n_diag, int64_t *a_split,
+                               uint64_t *n_fallback, void *stream);
+/* Save / load the model (features, hidden units, window, seed, parameters)
+   in a small binary file; load creates a new handle on the current device. */
+mp_status mp_lp_save(mp_lp h, const char *path);
+mp_status mp_lp_load(mp_lp *h, const char *path);
+
+/*
  * Kernel variant selection (used by the autotuner and by tests that compare
  * variants).  Applies to later calls of the named operation on every thread;
  * it must not be changed while another thread is inside a library call.

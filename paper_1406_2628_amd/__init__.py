@@ -61,6 +61,24 @@ def _declare(L):
         "mp_timing_query": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_int64)], i32),
         "mp_stats_query": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], i32),
+        "mp_lp_create": ([ctypes.POINTER(p), i32, i32, ctypes.c_uint64], i32),
+        "mp_lp_destroy": ([p], None),
+        "mp_lp_num_params": ([p], i32),
+        "mp_lp_shape": ([p, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "mp_lp_get_params": ([p, p, i32], i32),
+        "mp_lp_set_params": ([p, p, i32], i32),
+        "mp_lp_set_window": ([p, i64], i32),
+        "mp_lp_window": ([p], i64),
+        "mp_lp_examples": ([p, i32, p, i64, p, i64, i64, ctypes.c_uint64, p, p, p, p, p], i32),
+        "mp_lp_forward": ([p, p, i64, p, p], i32),
+        "mp_lp_grad": ([p, p, p, i64, p, p, p], i32),
+        "mp_lp_adam_step": ([p, p, p, i64, ctypes.c_float, p], i32),
+        "mp_lp_train": ([p, i32, p, p, p, p, i32, i64, i32, ctypes.c_float,
+                         ctypes.POINTER(ctypes.c_float), p], i32),
+        "mp_lp_calibrate": ([p, i32, p, i64, p, i64, i64, ctypes.POINTER(ctypes.c_int64), p], i32),
+        "mp_partition_learned": ([p, i32, p, i64, p, i64, p, i64, p, p, p], i32),
+        "mp_lp_save": ([p, ctypes.c_char_p], i32),
+        "mp_lp_load": ([ctypes.POINTER(p), ctypes.c_char_p], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -222,3 +240,118 @@ def sort(keys: torch.Tensor, vals: torch.Tensor | None = None, ws: torch.Tensor 
     _check(lib().mp_sort(kt, vt, _ptr(keys), _ptr(vals), keys.numel(), _ptr(ws),
                          0 if ws is None else ws.numel(), _stream(keys.device)))
     return keys if vals is None else (keys, vals)
+
+
+class LearnedPartitioner:
+    """Handle of the learned split predictor (mp_lp_*): an FP32 MLP whose
+    prediction bounds the exact split search; outputs equal ``partition``."""
+
+    def __init__(self, hidden: int = 32, features: int = 5, seed: int = 0, _handle=None):
+        self._h = ctypes.c_void_p()
+        if _handle is not None:
+            self._h = _handle
+        else:
+            _check(lib().mp_lp_create(ctypes.byref(self._h), hidden, features, seed))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and h.value and _lib is not None:
+            _lib.mp_lp_destroy(h)
+            self._h = ctypes.c_void_p()
+
+    @property
+    def num_params(self) -> int:
+        return lib().mp_lp_num_params(self._h)
+
+    @property
+    def window(self) -> int:
+        return lib().mp_lp_window(self._h)
+
+    @window.setter
+    def window(self, w: int):
+        _check(lib().mp_lp_set_window(self._h, w))
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.num_params, dtype=np.float32)
+        _check(lib().mp_lp_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p), len(out)))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        arr = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().mp_lp_set_params(self._h, arr.ctypes.data_as(ctypes.c_void_p), len(arr)))
+
+    def examples(self, A, B, K: int, seed: int = 1):
+        """(X, r, diag, split) device tensors for K stratified diagonals of (A, B)."""
+        kt = _key_dtype(A, B)
+        F = self.shape[0]
+        X = torch.empty((K, F), dtype=torch.float32, device=A.device)
+        r = torch.empty(K, dtype=torch.float32, device=A.device)
+        d = torch.empty(K, dtype=torch.int64, device=A.device)
+        s = torch.empty(K, dtype=torch.int64, device=A.device)
+        _check(lib().mp_lp_examples(self._h, kt, _ptr(A), A.numel(), _ptr(B), B.numel(), K, seed,
+                                    _ptr(X), _ptr(r), _ptr(d), _ptr(s), _stream(A.device)))
+        return X, r, d, s
+
+    @property
+    def shape(self):
+        """(features, hidden units)."""
+        f, h = ctypes.c_int(), ctypes.c_int()
+        _check(lib().mp_lp_shape(self._h, ctypes.byref(f), ctypes.byref(h)))
+        return f.value, h.value
+
+    def forward(self, X):
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(lib().mp_lp_forward(self._h, _ptr(X), X.shape[0], _ptr(y), _stream(X.device)))
+        return y
+
+    def grad(self, X, r):
+        g = torch.empty(self.num_params, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        _check(lib().mp_lp_grad(self._h, _ptr(X), _ptr(r), X.shape[0], _ptr(g), _ptr(loss),
+                                _stream(X.device)))
+        return g, loss
+
+    def adam_step(self, X, r, lr: float):
+        _check(lib().mp_lp_adam_step(self._h, _ptr(X), _ptr(r), X.shape[0], lr, _stream(X.device)))
+
+    def train(self, sets, k_diag: int = 1 << 14, epochs: int = 4000, lr: float = 1e-2) -> float:
+        """Train on a list of (A, B) device tensor pairs; returns the final loss."""
+        kt = _key_dtype(*[t for ab in sets for t in ab])
+        n = len(sets)
+        As = (ctypes.c_void_p * n)(*[a.data_ptr() for a, _ in sets])
+        Bs = (ctypes.c_void_p * n)(*[b.data_ptr() for _, b in sets])
+        nas = (ctypes.c_int64 * n)(*[a.numel() for a, _ in sets])
+        nbs = (ctypes.c_int64 * n)(*[b.numel() for _, b in sets])
+        loss = ctypes.c_float()
+        _check(lib().mp_lp_train(self._h, kt, As, nas, Bs, nbs, n, k_diag, epochs, lr,
+                                 ctypes.byref(loss), _stream(sets[0][0].device)))
+        return loss.value
+
+    def calibrate(self, A, B, n_diag: int = 1 << 16) -> int:
+        """Set the window from a held-out pair; returns the largest validation error."""
+        kt = _key_dtype(A, B)
+        err = ctypes.c_int64()
+        _check(lib().mp_lp_calibrate(self._h, kt, _ptr(A), A.numel(), _ptr(B), B.numel(), n_diag,
+                                     ctypes.byref(err), _stream(A.device)))
+        return err.value
+
+    def partition(self, A, B, diag, out=None, fallbacks=None):
+        """Same result as ``partition``; ``fallbacks`` (uint64 device scalar) counts misses."""
+        kt = _key_dtype(A, B)
+        if out is None:
+            out = torch.empty(diag.numel(), dtype=torch.int64, device=A.device)
+        _check(lib().mp_partition_learned(self._h, kt, _ptr(A), A.numel(), _ptr(B), B.numel(),
+                                          _ptr(diag), diag.numel(), _ptr(out), _ptr(fallbacks),
+                                          _stream(A.device)))
+        return out
+
+    def save(self, path: str):
+        _check(lib().mp_lp_save(self._h, path.encode()))
+
+    @classmethod
+    def load(cls, path: str) -> "LearnedPartitioner":
+        h = ctypes.c_void_p()
+        _check(lib().mp_lp_load(ctypes.byref(h), path.encode()))
+        return cls(_handle=h)

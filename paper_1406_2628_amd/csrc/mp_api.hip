@@ -71,6 +71,14 @@ int op_index(const char *name) {
 
 }  // namespace
 
+mp_status set_error(mp_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
 int device_cu_count() {
   static std::mutex mu;
   static std::vector<int> cache;

@@ -105,6 +105,9 @@ class KernelTimer {
   hipEvent_t start_ = nullptr;
 };
 
+// Record the message returned by mp_last_error() (this thread) and return st.
+mp_status set_error(mp_status st, const char *fmt, ...);
+
 // Device counters [tiles, window reloads] of the persistent kernels while
 // timing is enabled, nullptr otherwise.
 unsigned long long *stats_device_ptr();

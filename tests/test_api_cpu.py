@@ -74,6 +74,49 @@ def test_merge_kv_argument_errors(L):
     assert L.mp_merge_kv(MP_U32, MP_U32, ak, av, 4, bk, bv, 4, sk, P(0x20000), None) == OVERLAP
 
 
+def test_learned_argument_errors(L):
+    h = ctypes.c_void_p()
+    assert L.mp_lp_create(ctypes.byref(h), 0, 5, 1) == INVALID
+    assert L.mp_lp_create(ctypes.byref(h), 65, 5, 1) == INVALID
+    assert L.mp_lp_create(ctypes.byref(h), 32, 2, 1) == INVALID
+    assert L.mp_lp_create(None, 32, 5, 1) == INVALID
+    assert L.mp_lp_set_window(None, 5) == INVALID
+    assert L.mp_lp_window(None) == -1
+    assert L.mp_partition_learned(None, MP_F32, None, 0, None, 0, None, 0, None, None, None) == INVALID
+    assert L.mp_lp_load(ctypes.byref(h), b"/nonexistent/model") == INVALID
+
+
+def test_sort_and_batched_argument_errors(L):
+    k, ws = P(0x10000), P(0x80000)
+    assert L.mp_sort(MP_U32, MP_NONE, k, None, 100_000, None, 0, None) == WORKSPACE
+    need = L.mp_sort_workspace_bytes(MP_U32, MP_U32, 1000)
+    assert need >= 1000 * 8
+    assert L.mp_sort(MP_U32, MP_U32, k, None, 1000, ws, need, None) == INVALID
+    assert L.mp_sort(MP_U32, MP_NONE, k, P(0x20000), 1000, ws, need, None) == INVALID
+    assert L.mp_sort(MP_U32, MP_NONE, k, None, 1000, P(0x10000 + 64), need, None) == OVERLAP
+    assert L.mp_sort(MP_U32, MP_U64, k, P(0x20000), 1000, ws, need, None) == UNSUPPORTED
+    assert L.mp_sort(MP_U32, MP_NONE, k, None, 1, None, 0, None) == OK
+    a, ao, b, bo, s = (P(x) for x in (0x10000, 0x20000, 0x30000, 0x40000, 0x50000))
+    assert L.mp_merge_batched(MP_I32, a, ao, b, bo, -1, 0, 0, s, None, 0, None) == INVALID
+    assert L.mp_merge_batched(MP_I32, a, ao, b, bo, 0, 5, 0, s, None, 0, None) == INVALID
+    assert L.mp_merge_batched(MP_I32, a, None, b, bo, 3, 5, 5, s, None, 0, None) == INVALID
+    assert L.mp_merge_batched(MP_I32, a, ao, b, bo, 3, 5, 5, P(0x10000 + 8), None, 0, None) == OVERLAP
+    assert L.mp_merge_batched(MP_I32, None, None, None, None, 0, 0, 0, None, None, 0, None) == OK
+
+
+def test_config_errors(L):
+    import paper_1406_2628_amd as mp
+    with pytest.raises(mp.MergePathError):
+        mp.set_config("nonsense", 2)
+    with pytest.raises(mp.MergePathError):
+        mp.set_config("merge", 3)
+    with pytest.raises(mp.MergePathError):
+        mp.set_config("batched", 1)
+    with pytest.raises(mp.MergePathError):
+        mp.set_config("sort", 2, 256, 12)
+    mp.set_config("merge", None)
+
+
 def test_partition_argument_errors(L):
     a, b, d, o = P(0x10000), P(0x20000), P(0x30000), P(0x40000)
     assert L.mp_partition(0, a, 4, b, 4, d, 4, o, None) == UNSUPPORTED

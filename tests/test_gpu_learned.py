@@ -1,0 +1,198 @@
+"""GPU tests of the learned split predictor: network kernels against the
+float64 oracle, and split output identical to the plain search."""
+import os
+
+import numpy as np
+import pytest
+
+import mp_inputs as gen
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+F, H = 5, 32
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1406_2628_amd as mp
+    mp.lib()
+    return mp
+
+
+def _rand_model(mp, seed):
+    g = np.random.default_rng(seed)
+    lp = mp.LearnedPartitioner(H, F, seed)
+    p = (g.normal(size=lp.num_params) * 0.8).astype(np.float32)
+    lp.set_params(p)
+    return lp, p.astype(np.float64)
+
+
+def _features_np(d, na, nb):
+    t = d / (na + nb)
+    return np.stack([t, np.sin(2 * np.pi * t), np.cos(2 * np.pi * t),
+                     np.sin(4 * np.pi * t), np.cos(4 * np.pi * t)], 1)
+
+
+def _prior_np(d, na, nb):
+    a = np.rint(d * na / (na + nb)).astype(np.int64)
+    return np.clip(a, np.maximum(0, d - nb), np.minimum(d, na))
+
+
+def test_forward_matches_oracle(mp):
+    import torch
+    from gpu_util import dev, host
+    lp, p = _rand_model(mp, 1)
+    X = np.random.default_rng(2).uniform(-1, 1, (3000, F)).astype(np.float32)
+    got = host(lp.forward(dev(X)))
+    want = mlp.forward(p, X.astype(np.float64), H)
+    assert np.max(np.abs(got - want)) < 1e-4 * (1 + np.max(np.abs(want)))
+
+
+def test_grad_matches_oracle_and_is_deterministic(mp):
+    from gpu_util import dev, host
+    lp, p = _rand_model(mp, 3)
+    g = np.random.default_rng(4)
+    X = g.uniform(-1, 1, (5000, F)).astype(np.float32)
+    r = g.normal(size=5000).astype(np.float32)
+    dX, dr = dev(X), dev(r)
+    g1, l1 = lp.grad(dX, dr)
+    g2, l2 = lp.grad(dX, dr)
+    g1, l1, g2 = host(g1), host(l1), host(g2)
+    assert g1.tobytes() == g2.tobytes()          # fixed-order reduction
+    loss, want = mlp.loss_and_grad(p, X.astype(np.float64), r.astype(np.float64), H)
+    scale = np.max(np.abs(want))
+    assert np.max(np.abs(g1 - want)) < 1e-4 * scale
+    assert abs(l1[0] - loss) < 1e-4 * loss
+
+
+def test_adam_step_matches_oracle(mp):
+    from gpu_util import dev, host
+    lp, p = _rand_model(mp, 5)
+    g = np.random.default_rng(6)
+    X = g.uniform(-1, 1, (2000, F)).astype(np.float32)
+    r = g.normal(size=2000).astype(np.float32)
+    _, grad = mlp.loss_and_grad(p, X.astype(np.float64), r.astype(np.float64), H)
+    want, m, v = mlp.adam_step(p, grad, np.zeros_like(p), np.zeros_like(p), t=1, lr=1e-3)
+    lp.adam_step(dev(X), dev(r), 1e-3)
+    got = lp.get_params()
+    assert np.max(np.abs(got - want)) < 2e-5
+
+
+def test_examples_match_oracle(mp, orc):
+    from gpu_util import dev, host
+    A, B = gen.f32_mixture_pair(300_000, 200_000, 51)
+    lp = mp.LearnedPartitioner(H, F, 7)
+    X, r, d, s = lp.examples(dev(A), dev(B), 4096, seed=9)
+    d, s, X, r = host(d), host(s), host(X), host(r)
+    assert np.all((d >= 0) & (d <= len(A) + len(B)))
+    assert np.array_equal(s, orc.partition(A, B, d))
+    assert np.max(np.abs(X - _features_np(d, len(A), len(B)))) < 2e-6
+    want_r = (s - _prior_np(d, len(A), len(B))) / len(A)
+    assert np.max(np.abs(r - want_r)) < 1e-6
+
+
+@pytest.fixture(scope="module")
+def trained(mp):
+    """A model trained on four seeds and calibrated on a fifth (small arrays)."""
+    from gpu_util import dev
+    n = 1 << 18
+    sets = [tuple(map(dev, gen.f32_mixture_pair(n, n, s))) for s in (51, 52, 53, 54)]
+    lp = mp.LearnedPartitioner(H, F, 11)
+    loss0 = None
+    X, r, _, _ = lp.examples(*sets[0], 2048)
+    _, l = lp.grad(X, r)
+    loss0 = float(l.cpu()[0])
+    loss = lp.train(sets, k_diag=4096, epochs=600, lr=1e-2)
+    A, B = map(dev, gen.f32_mixture_pair(n, n, 59))
+    err = lp.calibrate(A, B, 1 << 14)
+    return lp, loss0, loss, err, n
+
+
+def test_training_reduces_loss(trained):
+    lp, loss0, loss, err, n = trained
+    assert loss < 0.2 * loss0
+    assert lp.window == err + err // 4 + 1
+    assert err < n // 4
+
+
+def _check_identical(mp, orc, lp, A, B, diag, expect_fallback=None):
+    import torch
+    from gpu_util import dev, host
+    dA, dB, dd = dev(A), dev(B), dev(diag)
+    fb = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    got = host(lp.partition(dA, dB, dd, fallbacks=fb))
+    plain = host(mp.partition(dA, dB, dd))
+    assert np.array_equal(got, plain)
+    assert np.array_equal(got, orc.partition(A, B, diag))
+    n_fb = int(fb.cpu().numpy()[0])
+    if expect_fallback is True:
+        assert n_fb > 0
+    elif expect_fallback is False:
+        assert n_fb == 0
+    return n_fb
+
+
+def test_learned_partition_identical(mp, orc, trained):
+    lp, _, _, _, n = trained
+    A, B = gen.f32_mixture_pair(n, n, 60)
+    diag = np.concatenate([[0, 1, 2 * n - 1, 2 * n],
+                           np.random.default_rng(3).integers(0, 2 * n + 1, 20000)]).astype(np.int64)
+    _check_identical(mp, orc, lp, A, B, diag)
+
+
+def test_forced_fallback_zero_window(mp, orc, trained):
+    lp, _, _, _, n = trained
+    w = lp.window
+    try:
+        lp.window = 0
+        A, B = gen.f32_mixture_pair(n, n, 60)
+        diag = np.random.default_rng(4).integers(0, 2 * n + 1, 5000).astype(np.int64)
+        _check_identical(mp, orc, lp, A, B, diag, expect_fallback=True)
+    finally:
+        lp.window = w
+
+
+def test_garbage_model_still_exact(mp, orc):
+    lp = mp.LearnedPartitioner(H, F, 1)
+    p = np.full(lp.num_params, 1e30, np.float32)
+    p[::7] = np.nan
+    lp.set_params(p)
+    lp.window = 3
+    for dt in (gen.U32, gen.I32, gen.U64, gen.F32):
+        A, B = gen.uniform_pair(40_000, 70_001, 8, dt)
+        diag = np.random.default_rng(5).integers(0, len(A) + len(B) + 1, 3000).astype(np.int64)
+        _check_identical(mp, orc, lp, A, B, diag, expect_fallback=True)
+
+
+def test_other_distribution_and_skew(mp, orc, trained):
+    """A model trained on one distribution, used on another: still exact."""
+    lp, _, _, _, n = trained
+    for A, B in (gen.disjoint_pair(50_000, 80_000, 3), gen.dups_pair(70_000, 10, 4, hi=9)):
+        A, B = A.astype(np.float32), B.astype(np.float32)
+        diag = np.arange(0, len(A) + len(B) + 1, 37, dtype=np.int64)
+        _check_identical(mp, orc, lp, A, B, diag)
+
+
+def test_save_load_roundtrip(mp, trained, tmp_path):
+    lp, _, _, _, _ = trained
+    path = str(tmp_path / "model.mplp")
+    lp.save(path)
+    lp2 = mp.LearnedPartitioner.load(path)
+    assert lp2.shape == lp.shape and lp2.window == lp.window
+    assert lp2.get_params().tobytes() == lp.get_params().tobytes()
+    with open(path, "r+b") as f:
+        f.write(b"XXXX")
+    with pytest.raises(mp.MergePathError, match="STATE"):
+        mp.LearnedPartitioner.load(path)
+
+
+def test_uncalibrated_raises(mp):
+    from gpu_util import dev
+    lp = mp.LearnedPartitioner(H, F, 2)
+    A, B = gen.uniform_pair(100, 100, 1)
+    with pytest.raises(mp.MergePathError, match="STATE"):
+        lp.partition(dev(A), dev(B), dev(np.arange(10, dtype=np.int64)))
