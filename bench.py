@@ -2,16 +2,23 @@
 
 Headline: merge of two sorted uint32 arrays, |A| = |B| = 2^28, keys uniform
 in [0, 2^32) (seed 11), inputs resident in HBM, output preallocated.  One
-step = one full mp_merge call (tile split search + tile merge).  Prints one
-JSON line with the throughput (Gkeys/s merged), the roofline of the dominant
-kernel timed with HIP events on its own stream, and the single-core oracle
-baseline timed on the host.
+step = one mp_merge call (one persistent kernel: per-workgroup split search,
+LDS windows, per-lane split search, serial merge, coalesced stores).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints ONE JSON line: throughput (Gkeys/s merged), the roofline of the merge
+kernel timed with HIP events that the library records on its launch stream,
+the single-core oracle baseline timed on the host, and under "extras" the
+other workloads: key-value merges, merge sort, batched merge and the learned
+split predictor against the plain split search.  Every output is checked
+(bit-exact against the oracle, or for the 2^28 sort against numpy's sort,
+which the oracle's own tests pin).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs a,b,...]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,81 +30,98 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gkeys/s merged & % HBM peak (2^28+2^28 u32); learned vs bsearch split time"
+LEGS = ("headline", "kv", "sort", "batched", "learned")
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "merge_stream_u32_2p28.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1406_2628_amd", "csrc", f)
+                  for f in ("mp_stream.hip", "mp_device.h")]
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
 def time_steps(fn, steps, warmup):
+    """Mean ms per call over `steps` back-to-back calls after `warmup` calls."""
     import torch
     for _ in range(warmup):
         fn()
-    torch.cuda.synchronize()
+    sync()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(steps):
         fn()
     stop.record()
-    torch.cuda.synchronize()
+    sync()
     return start.elapsed_time(stop) / steps
 
 
-def cpu_baseline_merge(A, B, budget_s=10.0):
-    """The oracle's sequential merge on the host, repeated for about budget_s."""
-    import oracle
-    times = []
-    t_all = time.perf_counter()
-    while True:
-        t0 = time.perf_counter()
-        S = oracle.merge(A, B)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_all > budget_s or len(times) >= 8:
-            break
-    times.sort()
-    med = times[len(times) // 2]
-    return S, med, len(times)
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--log2n", type=int, default=28, help="log2 of |A| = |B|")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-verify", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="time only the reference copy of the same byte count")
-    args = ap.parse_args()
-
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (the merge shards by diagonal "
-              "splits, but no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
+def time_each(fn, setup, reps, warmup=1):
+    """Median ms of fn() over reps, each preceded by an untimed setup()."""
     import numpy as np
+    import torch
+    ts = []
+    for r in range(warmup + reps):
+        setup()
+        sync()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        sync()
+        if r >= warmup:
+            ts.append(s.elapsed_time(e))
+    return float(np.median(ts))
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(x).cuda()
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    try:
+        fields = {}
+        for line in open(PROFILE_SUMMARY):
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+        if fields.get("kernel source sha256") != source_sha():
+            return None
+        return float(fields["HBM bytes per launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+# ---------------------------------------------------------------------------
+def leg_headline(args, out):
     import torch
 
     import mp_inputs as gen
     import paper_1406_2628_amd as mp
-
-    torch.cuda.set_device(0)
     na = nb = 1 << args.log2n
     seed = 11
-    log(f"bench: generating u32 inputs 2^{args.log2n}+2^{args.log2n} (seed {seed})")
+    log(f"bench: headline: generating u32 inputs 2^{args.log2n}+2^{args.log2n} (seed {seed})")
     A, B = gen.uniform_pair(na, nb, seed)
-    dA = torch.from_numpy(A).cuda()
-    dB = torch.from_numpy(B).cuda()
+    dA, dB = dev(A), dev(B)
     dS = torch.empty(na + nb, dtype=torch.uint32, device="cuda")
-    torch.cuda.synchronize()
-
     n_out = na + nb
-    alg_bytes = n_out * 4 * 2   # every input key read once, every output key written once
+    alg_bytes = n_out * 4 * 2  # each input key read once, each output key written once
 
     if args.copy_probe:
-        # Reference copy of the same byte count (counter calibration, copy ceiling).
         del dA, dB
         src = torch.empty(n_out * 4, dtype=torch.uint8, device="cuda")
         src.fill_(1)
@@ -105,26 +129,26 @@ def main():
         ms = time_steps(lambda: mp.copy(src, dst), args.steps, args.warmup)
         print(json.dumps({"probe": "copy", "bytes_moved": 2 * src.numel(), "ms": round(ms, 4),
                           "GBs": round(2 * src.numel() / ms / 1e6, 1)}), flush=True)
-        return
+        sys.exit(0)
 
-    log("bench: timing mp_merge")
+    log("bench: headline: timing mp_merge")
     step = lambda: mp.merge(dA, dB, out=dS)  # noqa: E731
     mp.timing_enable(False)
     ms = time_steps(step, args.steps, args.warmup)
-    # per-kernel durations over a second timed region: HIP events recorded by
-    # the library on the launch stream around each kernel
+    # kernel durations over a second timed region: HIP events the library
+    # records on the launch stream around each kernel
     mp.timing_enable(True)
     time_steps(step, args.steps, 0)
     k_ms, k_n = mp.timing_query("merge_stream")
+    tiles, reloads = mp.stats_query()
     mp.timing_enable(False)
     kern_ms = k_ms / max(1, k_n)
-
-    value = n_out / (ms * 1e-3) / 1e9
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    traffic = profiled_traffic()
 
-    result = {
+    out.update({
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": round(n_out / (ms * 1e-3) / 1e9, 2),
         "unit": "Gkeys/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -135,31 +159,220 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic (seeded uniform u32 keys, sorted)",
-        "config": {"workload": f"merge u32 2^{args.log2n}+2^{args.log2n} uniform keys, seed {seed}",
-                   "na": na, "nb": nb},
+        "config": {"workload": f"merge of sorted u32 arrays, 2^{args.log2n}+2^{args.log2n} "
+                               f"uniform keys, seed {seed}", "na": na, "nb": nb},
         "hbm_frac_step": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": {"bound": "hbm", "kernel": "merge_stream_kernel",
+        "roofline": {"bound": "hbm", "kernel": "merge_pairs_kernel (single pair)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel_ms": round(kern_ms, 4)},
-    }
-
-    if not args.no_verify or not args.no_cpu_baseline:
-        S = dS.cpu().numpy()
-        if args.no_cpu_baseline:
-            import oracle
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                     "traffic_unit": "GB per launch", "algorithmic_GB": round(alg_bytes / 1e9, 4),
+                     "kernel_ms": round(kern_ms, 4),
+                     "window_reload_rate": round(reloads / max(1, tiles), 6)},
+    })
+    S = dS.cpu().numpy()
+    del dA, dB, dS
+    if args.no_cpu_baseline:
+        import oracle
+        ref = oracle.merge(A, B)
+    else:
+        log("bench: headline: oracle merge on the host (cpu baseline and verification)")
+        import oracle
+        times = []
+        t_all = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
             ref = oracle.merge(A, B)
-        else:
-            log("bench: oracle merge on the host (cpu baseline + verification)")
-            ref, cpu_s, reps = cpu_baseline_merge(A, B)
-            result["cpu_baseline"] = {
-                "value": round(n_out / cpu_s / 1e9, 4), "unit": "Gkeys/s", "cores": 1,
-                "kind": "oracle",
-                "sample": f"full workload (2^{args.log2n}+2^{args.log2n} u32), median of {reps} runs, "
-                          f"1 of {os.cpu_count()} host threads"}
-        result["bit_exact"] = bool(S.tobytes() == ref.tobytes())
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_all > 10.0 or len(times) >= 8:
+                break
+        times.sort()
+        out["cpu_baseline"] = {
+            "value": round(n_out / times[len(times) // 2] / 1e9, 4), "unit": "Gkeys/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"the full headline workload, median of {len(times)} single-threaded runs "
+                      f"(1 of {os.cpu_count()} host threads)"}
+    out["bit_exact"] = bool(S.tobytes() == ref.tobytes())
 
-    print(json.dumps(result), flush=True)
+
+# ---------------------------------------------------------------------------
+def leg_kv(args, ex):
+    import torch
+
+    import mp_inputs as gen
+    import oracle
+    import paper_1406_2628_amd as mp
+    res = {}
+    n = 1 << args.log2n
+    cases = [("u32_uniform", 21, n), ("u32_dups_1024", 22, n), ("u32_disjoint", 23, n),
+             ("u64_uniform", 24, n // 2)]
+    for name, seed, m in cases:
+        log(f"bench: kv {name} 2^{m.bit_length() - 1}+2^{m.bit_length() - 1}")
+        if name == "u32_dups_1024":
+            A, B = gen.dups_pair(m, m, seed)
+        elif name == "u32_disjoint":
+            A, B = gen.disjoint_pair(m, m, seed)
+        else:
+            A, B = gen.uniform_pair(m, m, seed, gen.U64 if name.startswith("u64") else gen.U32)
+        va, vb = gen.index_payload(m, m)
+        dA, dB, dva, dvb = dev(A), dev(B), dev(va), dev(vb)
+        ok_ = torch.empty(2 * m, dtype=dA.dtype, device="cuda")
+        ov = torch.empty(2 * m, dtype=torch.uint32, device="cuda")
+        ms = time_steps(lambda: mp.merge_kv(dA, dva, dB, dvb, out_k=ok_, out_v=ov),
+                        max(3, args.steps // 2), 2)
+        gk, gv = ok_.cpu().numpy(), ov.cpu().numpy()
+        del dA, dB, dva, dvb, ok_, ov
+        wk, wv = oracle.merge_kv(A, va, B, vb)
+        bytes_ = 2 * m * (A.itemsize + 4) * 2
+        res[name] = {"n": 2 * m, "ms": round(ms, 4), "Gkeys_s": round(2 * m / ms / 1e6, 2),
+                     "hbm_frac": round(bytes_ / ms / 1e6 / HBM_PEAK_GBS, 4),
+                     "bit_exact": bool(gk.tobytes() == wk.tobytes() and gv.tobytes() == wv.tobytes())}
+    ex["kv"] = res
+
+
+def leg_sort(args, ex):
+    import numpy as np
+    import torch
+
+    import mp_inputs as gen
+    import paper_1406_2628_amd as mp
+    n = 1 << args.log2n
+    res = {}
+    for name, seed in (("u32_uniform", 31), ("u32_zipf_1.1", 32)):
+        log(f"bench: sort {name} 2^{args.log2n}")
+        keys = gen.unsorted_uniform(n, seed) if "uniform" in name else gen.zipf_keys(n, seed)
+        d0 = dev(keys)
+        dk = torch.empty_like(d0)
+        ws = torch.empty(mp.sort_workspace_bytes(torch.uint32, None, n), dtype=torch.uint8,
+                         device="cuda")
+        mp.timing_enable(True)
+        ms = time_each(lambda: mp.sort(dk, ws=ws), lambda: dk.copy_(d0), max(3, args.steps // 4))
+        bs, rd = mp.timing_query("blocksort"), mp.timing_query("sort_round")
+        mp.timing_enable(False)
+        got = dk.cpu().numpy()
+        del d0, dk, ws
+        rounds = int(np.ceil(np.log2(max(1, n / 2048))))
+        bytes_ = (1 + rounds) * n * 8
+        res[name] = {"n": n, "ms": round(ms, 4), "Gkeys_s": round(n / ms / 1e6, 3),
+                     "passes": 1 + rounds,
+                     "hbm_frac": round(bytes_ / ms / 1e6 / HBM_PEAK_GBS, 4),
+                     "blocksort_ms": round(bs[0] / max(1, bs[1]), 4),
+                     "round_ms": round(rd[0] / max(1, rd[1]), 4),
+                     "equals_numpy_sort": bool(np.array_equal(got, np.sort(keys)))}
+    ex["sort"] = res
+
+
+def leg_batched(args, ex):
+    import torch
+
+    import mp_inputs as gen
+    import oracle
+    import paper_1406_2628_amd as mp
+    n_pairs = 100_000 if args.log2n == 28 else max(10, 100_000 >> (28 - args.log2n))
+    log(f"bench: batched {n_pairs} pairs")
+    A, a_off, B, b_off = gen.batched_pairs(n_pairs, 41)
+    tot = len(A) + len(B)
+    dA, dB, da, db = dev(A), dev(B), dev(a_off), dev(b_off)
+    dS = torch.empty(tot, dtype=torch.int32, device="cuda")
+    mp.timing_enable(True)
+    ms = time_steps(lambda: mp.merge_batched(dA, da, dB, db, out=dS), args.steps, 2)
+    tiles, reloads = mp.stats_query()
+    mp.timing_enable(False)
+    got = dS.cpu().numpy()
+    del dA, dB, da, db, dS
+    ref = oracle.merge_batched(A, a_off, B, b_off)
+    ex["batched"] = {"pairs": n_pairs, "n": tot, "ms": round(ms, 4),
+                     "Gkeys_s": round(tot / ms / 1e6, 2),
+                     "hbm_frac": round(tot * 8 / ms / 1e6 / HBM_PEAK_GBS, 4),
+                     "window_reload_rate": round(reloads / max(1, tiles), 6),
+                     "bit_exact": bool(got.tobytes() == ref.tobytes())}
+
+
+def leg_learned(args, ex):
+    import numpy as np
+    import torch
+
+    import mp_inputs as gen
+    import oracle
+    import paper_1406_2628_amd as mp
+    n = 1 << (args.log2n + 1)          # |A| = |B| = 2^29 at the default size
+    n_train = max(1 << 16, n >> 7)     # training sets of the same family, smaller
+    res = {"n_per_array": n, "train_n_per_array": n_train}
+    log(f"bench: learned: training on 8 seeds of 2^{n_train.bit_length() - 1}")
+    sets = [gen.f32_mixture_pair_torch(n_train, n_train, s) for s in range(51, 59)]
+    lp = mp.LearnedPartitioner(32, 5, 7)
+    sync()
+    t0 = time.perf_counter()
+    loss = lp.train(sets, k_diag=1 << 14, epochs=4000, lr=1e-2)
+    res["train_s"] = round(time.perf_counter() - t0, 3)
+    res["train_loss"] = loss
+    del sets
+    log("bench: learned: calibrating on a held-out full-size pair (seed 59)")
+    A, B = gen.f32_mixture_pair_torch(n, n, 59)
+    res["max_val_err"] = lp.calibrate(A, B, 1 << 16)
+    res["window"] = lp.window
+    del A, B
+    torch.cuda.empty_cache()
+    log("bench: learned: timing on the evaluation pair (seed 60)")
+    A, B = gen.f32_mixture_pair_torch(n, n, 60)
+    N = 2 * n
+    sweep = {}
+    for logp in (12, 16, 18, 20):
+        P = 1 << logp
+        diag = (torch.arange(P + 1, device="cuda", dtype=torch.int64) * N) // P
+        out_p = torch.empty(P + 1, dtype=torch.int64, device="cuda")
+        out_l = torch.empty(P + 1, dtype=torch.int64, device="cuda")
+        fb = torch.zeros(1, dtype=torch.uint64, device="cuda")
+        t_plain = time_steps(lambda: mp.partition(A, B, diag, out=out_p), 10, 3)
+        t_learn = time_steps(lambda: lp.partition(A, B, diag, out=out_l), 10, 3)
+        fb.zero_()
+        lp.partition(A, B, diag, out=out_l, fallbacks=fb)
+        same = bool(torch.equal(out_p, out_l))
+        sweep[f"P=2^{logp}"] = {"plain_ms": round(t_plain, 4), "learned_ms": round(t_learn, 4),
+                                "speedup": round(t_plain / t_learn, 3), "identical": same,
+                                "fallbacks": int(fb.cpu().numpy()[0])}
+    res["sweep"] = sweep
+    # spot-check against the oracle on sampled diagonals (one sequential walk)
+    Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
+    ds = np.sort(np.random.default_rng(0).integers(0, N + 1, 256)).astype(np.int64)
+    got = lp.partition(A, B, dev(ds)).cpu().numpy()
+    res["oracle_spot_check_256"] = bool(np.array_equal(got, oracle.partition(Ah, Bh, ds)))
+    ex["learned"] = res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--log2n", type=int, default=28, help="log2 of |A| = |B| for the headline")
+    ap.add_argument("--legs", default=",".join(LEGS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time only the reference copy of the headline's byte count")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; a merge would shard by "
+              "splitting the output at G-1 diagonals, but no multi-GPU path is built. "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    legs = [x for x in args.legs.split(",") if x]
+    out = {}
+    leg_headline(args, out)
+    ex = {}
+    for name, fn in (("kv", leg_kv), ("sort", leg_sort), ("batched", leg_batched),
+                     ("learned", leg_learned)):
+        if name in legs:
+            fn(args, ex)
+            torch.cuda.empty_cache()
+    if ex:
+        out["extras"] = ex
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

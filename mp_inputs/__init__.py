@@ -200,3 +200,49 @@ def f32_mixture(n: int, g: np.random.Generator, mix: np.ndarray) -> np.ndarray:
 def f32_mixture_pair(na: int, nb: int, seed: int):
     g = rng(seed)
     return f32_mixture(na, g, MIX_A), f32_mixture(nb, g, MIX_B)
+
+
+def f32_mixture_torch(n: int, seed: int, mix: np.ndarray, device="cuda"):
+    """The f32 mixture recipe drawn with torch's generator on `device` (for
+    sizes where host generation is slow).  Same family as f32_mixture (same
+    weights, cluster geometry and signed-zero rate), different random stream."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def categorical(weights, count):
+        # inverse-CDF draw of `count` category indices
+        cdf = torch.cumsum(torch.as_tensor(weights, dtype=torch.float64, device=device), 0)
+        cdf = cdf / cdf[-1]
+        u = torch.rand(count, generator=g, device=device, dtype=torch.float64)
+        return torch.searchsorted(cdf, u, right=True).clamp(max=len(weights) - 1)
+
+    comp = categorical(mix, n)
+    x = torch.empty(n, dtype=torch.float64, device=device)
+    m = comp == 0
+    x[m] = torch.rand(int(m.sum()), generator=g, device=device, dtype=torch.float64) * 2e6 - 1e6
+    m = comp == 1
+    x[m] = torch.randn(int(m.sum()), generator=g, device=device, dtype=torch.float64) * 1e3
+    m = comp == 2
+    w = torch.arange(1, 2**20 + 1, dtype=torch.float64, device=device) ** (-1.1)
+    cdf = torch.cumsum(w, 0)
+    cdf /= cdf[-1].clone()
+    u = torch.rand(int(m.sum()), generator=g, device=device, dtype=torch.float64)
+    x[m] = (torch.searchsorted(cdf, u, right=True) + 1).clamp(max=2**20).to(torch.float64)
+    m = comp == 3
+    centres, sig, wts = (torch.tensor(a, device=device) for a in _clusters())
+    cid = categorical(wts, int(m.sum()))
+    x[m] = centres[cid] + sig[cid] * torch.randn(int(m.sum()), generator=g, device=device,
+                                                  dtype=torch.float64)
+    x = x.to(torch.float32)
+    nz = n // 1000
+    if nz:
+        idx = torch.randint(0, n, (nz,), generator=g, device=device)
+        signs = torch.rand(nz, generator=g, device=device) < 0.5
+        x[idx] = torch.where(signs, torch.tensor(0.0, device=device), torch.tensor(-0.0, device=device))
+    return torch.sort(x).values
+
+
+def f32_mixture_pair_torch(na: int, nb: int, seed: int, device="cuda"):
+    return (f32_mixture_torch(na, 2 * seed, MIX_A, device),
+            f32_mixture_torch(nb, 2 * seed + 1, MIX_B, device))
