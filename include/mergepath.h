@@ -250,6 +250,42 @@ typedef struct {
   int32_t margin;
 } mp_config;
 mp_status mp_set_config(const char *op, const mp_config *cfg);
+/* The configuration `op` currently uses (HOST output). */
+mp_status mp_get_config(const char *op, mp_config *cfg);
+
+/*
+ * Autotuner.  Times every compiled persistent (nt, vt) variant of an
+ * operation on the caller's own inputs (HIP events on `stream`: one warm-up
+ * call, then the median of `reps` calls), installs the fastest for later
+ * calls (as mp_set_config) and returns it in *best (HOST).  Arguments are
+ * those of the operation; outputs are overwritten.  mp_autotune_sort sorts
+ * `keys` (and `vals`) repeatedly, restoring them from keys_in / vals_in
+ * before every call.  Synchronises the stream.
+ */
+mp_status mp_autotune_merge(mp_dtype kt, mp_dtype vt, const void *Ak, const void *Av,
+                            int64_t na, const void *Bk, const void *Bv, int64_t nb,
+                            void *Sk, void *Sv, int reps, mp_config *best, void *stream);
+mp_status mp_autotune_batched(mp_dtype kt, const void *A, const int64_t *a_off,
+                              const void *B, const int64_t *b_off, int64_t n_pairs,
+                              int64_t total_a, int64_t total_b, void *S, int reps,
+                              mp_config *best, void *stream);
+mp_status mp_autotune_sort(mp_dtype kt, mp_dtype vt, const void *keys_in,
+                           const void *vals_in, void *keys, void *vals, int64_t n,
+                           void *ws, size_t ws_bytes, int reps, mp_config *best,
+                           void *stream);
+
+/*
+ * hipGraph mode (off by default).  While enabled, mp_sort and
+ * mp_merge_batched record their kernel launches into a hipGraph the first
+ * time they see a given argument tuple (pointers, sizes, dtypes, current
+ * configuration) and launch that graph on the caller's stream, then and on
+ * every later identical call; kernels read the buffers when the graph runs.
+ * At most 32 graphs are kept (least recently used evicted).  Calls that
+ * overlap on different threads must not share buffers (as without graphs).
+ */
+mp_status mp_graph_enable(int on);
+mp_status mp_graph_clear(void);
+int64_t mp_graph_count(void);
 
 /*
  * mp_copy -- plain streaming copy of n_bytes (multiple of 16) from src to

@@ -55,6 +55,13 @@ def _declare(L):
         "mp_sort_workspace_bytes": ([i32, i32, i64], sz),
         "mp_sort": ([i32, i32, p, p, i64, p, sz, p], i32),
         "mp_set_config": ([ctypes.c_char_p, ctypes.c_void_p], i32),
+        "mp_get_config": ([ctypes.c_char_p, ctypes.c_void_p], i32),
+        "mp_graph_enable": ([i32], i32),
+        "mp_graph_clear": ([], i32),
+        "mp_graph_count": ([], i64),
+        "mp_autotune_merge": ([i32, i32, p, p, i64, p, p, i64, p, p, i32, p, p], i32),
+        "mp_autotune_batched": ([i32, p, p, p, p, i64, i64, i64, p, i32, p, p], i32),
+        "mp_autotune_sort": ([i32, i32, p, p, p, p, i64, p, sz, i32, p, p], i32),
         "mp_copy": ([p, p, i64, i32, i32, p], i32),
         "mp_timing_enable": ([i32], i32),
         "mp_timing_reset": ([], i32),
@@ -101,6 +108,26 @@ def set_config(op: str, mode: int | None = None, nt: int = 256, vt: int = 16, gr
     else:
         cfg = Config(mode, nt, vt, grid, margin)
         _check(lib().mp_set_config(op.encode(), ctypes.cast(ctypes.byref(cfg), ctypes.c_void_p)))
+
+
+def graph_mode(on: bool = True):
+    """Record sort and batched launches into cached hipGraphs (see mp_graph_enable)."""
+    _check(lib().mp_graph_enable(1 if on else 0))
+
+
+def graph_clear():
+    _check(lib().mp_graph_clear())
+
+
+def graph_count() -> int:
+    return lib().mp_graph_count()
+
+
+def get_config(op: str):
+    """(mode, nt, vt, grid, margin) that ``op`` currently uses."""
+    cfg = Config()
+    _check(lib().mp_get_config(op.encode(), ctypes.cast(ctypes.byref(cfg), ctypes.c_void_p)))
+    return (cfg.mode, cfg.nt, cfg.vt, cfg.grid, cfg.margin)
 
 
 def copy(src: torch.Tensor, dst: torch.Tensor, unroll: int = 0, grid: int = 0):

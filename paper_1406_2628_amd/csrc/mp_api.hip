@@ -1,6 +1,7 @@
 // C ABI layer: host-side argument validation, dtype dispatch and launches.
 // Validation never touches device memory, so every argument error is
 // reported before any work is enqueued.
+#include <algorithm>
 #include <mutex>
 #include <stdarg.h>
 #include <stdio.h>
@@ -309,12 +310,20 @@ mp_status mp_merge_batched(mp_dtype kt, const void *A, const int64_t *a_off,
   const mp_config cfg = current_config(kOpBatched);
   const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipSuccess;
-  dispatch_key(kt, [&](auto k) {
-    using K = decltype(k);
-    KernelTimer timer("merge_batched", s);
-    e = launch_merge_batched<K>(sc, (const K *)A, a_off, (const K *)B, b_off, n_pairs,
-                                total_a, total_b, (K *)S, s);
+  const std::vector<uint64_t> key = {
+      1, (uint64_t)kt, (uint64_t)(uintptr_t)A, (uint64_t)(uintptr_t)a_off,
+      (uint64_t)(uintptr_t)B, (uint64_t)(uintptr_t)b_off, (uint64_t)n_pairs,
+      (uint64_t)total_a, (uint64_t)total_b, (uint64_t)(uintptr_t)S,
+      (uint64_t)cfg.nt, (uint64_t)cfg.vt, (uint64_t)cfg.grid, (uint64_t)(uint32_t)cfg.margin};
+  hipError_t e = run_maybe_graph(key, s, [&](hipStream_t st) {
+    hipError_t ee = hipSuccess;
+    dispatch_key(kt, [&](auto k) {
+      using K = decltype(k);
+      KernelTimer timer("merge_batched", st);
+      ee = launch_merge_batched<K>(sc, (const K *)A, a_off, (const K *)B, b_off, n_pairs,
+                                   total_a, total_b, (K *)S, st);
+    });
+    return ee;
   });
   if (e == hipErrorNotSupported)
     return fail(MP_ERR_UNSUPPORTED, "%s: configuration nt=%d vt=%d not compiled in", fn, cfg.nt, cfg.vt);
@@ -358,30 +367,158 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
   const mp_config cfg = current_config(kOpSort);
   const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipSuccess;
   int rounds = 0;
   for (int64_t w = kSortBlock; w < n; w <<= 1) ++rounds;
-  dispatch_key(kt, [&](auto k) {
-    using K = decltype(k);
-    K *kb[2] = {(K *)keys, (K *)ws};
-    uint32_t *vb[2] = {(uint32_t *)vals,
-                       kv ? (uint32_t *)((char *)ws + sort_ws_keys_bytes(es, n)) : nullptr};
-    // Choose where the sorted blocks land so that the last round writes the
-    // caller's arrays.
-    int cur = rounds % 2;
-    {
-      KernelTimer timer("blocksort", s);
-      e = launch_blocksort<K>((const K *)keys, (const uint32_t *)vals, kb[cur], vb[cur], n, s);
-    }
-    for (int lw = kSortBlockLog2; e == hipSuccess && ((int64_t)1 << lw) < n; ++lw) {
-      KernelTimer timer("sort_round", s);
-      e = launch_sort_round<K>(sc, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, lw, s);
-      cur ^= 1;
-    }
+  const std::vector<uint64_t> key = {
+      2, (uint64_t)kt, (uint64_t)vt, (uint64_t)(uintptr_t)keys, (uint64_t)(uintptr_t)vals,
+      (uint64_t)n, (uint64_t)(uintptr_t)ws, (uint64_t)cfg.nt, (uint64_t)cfg.vt,
+      (uint64_t)cfg.grid, (uint64_t)(uint32_t)cfg.margin};
+  hipError_t e = run_maybe_graph(key, s, [&](hipStream_t st) {
+    hipError_t ee = hipSuccess;
+    dispatch_key(kt, [&](auto k) {
+      using K = decltype(k);
+      K *kb[2] = {(K *)keys, (K *)ws};
+      uint32_t *vb[2] = {(uint32_t *)vals,
+                         kv ? (uint32_t *)((char *)ws + sort_ws_keys_bytes(es, n)) : nullptr};
+      // Choose where the sorted blocks land so that the last round writes the
+      // caller's arrays.
+      int cur = rounds % 2;
+      {
+        KernelTimer timer("blocksort", st);
+        ee = launch_blocksort<K>((const K *)keys, (const uint32_t *)vals, kb[cur], vb[cur], n, st);
+      }
+      for (int lw = kSortBlockLog2; ee == hipSuccess && ((int64_t)1 << lw) < n; ++lw) {
+        KernelTimer timer("sort_round", st);
+        ee = launch_sort_round<K>(sc, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, lw, st);
+        cur ^= 1;
+      }
+    });
+    return ee;
   });
   if (e == hipErrorNotSupported)
     return fail(MP_ERR_UNSUPPORTED, "%s: configuration nt=%d vt=%d not compiled in", fn, cfg.nt, cfg.vt);
   return e == hipSuccess ? MP_OK : hip_fail(e, "mp_sort launch");
+}
+
+}  // extern "C"
+
+// ---- autotuner ---------------------------------------------------------------
+//
+// Times every compiled persistent variant of an operation on the caller's
+// inputs (HIP events on the caller's stream; one warm-up call, then the
+// median of `reps` calls), installs the fastest with mp_set_config and
+// returns it.  `setup`, when given, runs untimed before every call (the sort
+// restores its unsorted input).
+
+static const int kTuneShapes[][2] = {{256, 16}, {256, 12}, {256, 8}, {128, 16}, {512, 8}};
+
+template <typename Run, typename Setup>
+static mp_status autotune(Op op, int reps, hipStream_t s, Run run, Setup setup, mp_config *best) {
+  if (reps < 1 || reps > 1000) return fail(MP_ERR_INVALID_ARG, "autotune: reps must be in [1, 1000]");
+  const mp_config saved = g_config[op];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(MP_ERR_HIP, "autotune: event creation failed");
+  }
+  float best_ms = 0.f;
+  bool have = false;
+  mp_status st = MP_OK;
+  for (const auto &shape : kTuneShapes) {
+    mp_config c{2, shape[0], shape[1], 0, 0};
+    if (op == kOpSort) {
+      const int64_t t = (int64_t)c.nt * c.vt;
+      if ((t & (t - 1)) != 0 || t > 2 * kSortBlock) continue;
+    }
+    g_config[op] = c;
+    std::vector<float> ts;
+    for (int r = 0; r <= reps && st == MP_OK; ++r) {
+      setup();
+      if (hipEventRecord(e0, s) != hipSuccess) { st = fail(MP_ERR_HIP, "autotune: event"); break; }
+      const mp_status rs = run();
+      if (rs == MP_ERR_UNSUPPORTED) break;
+      if (rs != MP_OK) { st = rs; break; }
+      float ms = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(MP_ERR_HIP, "autotune: timing");
+        break;
+      }
+      if (r > 0) ts.push_back(ms);
+    }
+    if (st != MP_OK) break;
+    if (ts.empty()) continue;
+    std::sort(ts.begin(), ts.end());
+    const float med = ts[ts.size() / 2];
+    if (!have || med < best_ms) {
+      best_ms = med;
+      *best = c;
+      have = true;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != MP_OK || !have) {
+    g_config[op] = saved;
+    return st != MP_OK ? st : fail(MP_ERR_UNSUPPORTED, "autotune: no variant ran");
+  }
+  g_config[op] = *best;
+  return MP_OK;
+}
+
+extern "C" {
+
+mp_status mp_autotune_merge(mp_dtype kt, mp_dtype vt, const void *Ak, const void *Av,
+                            int64_t na, const void *Bk, const void *Bv, int64_t nb, void *Sk,
+                            void *Sv, int reps, mp_config *best, void *stream) {
+  if (!best) return fail(MP_ERR_INVALID_ARG, "mp_autotune_merge: NULL result");
+  auto run = [&]() {
+    return vt == MP_NONE ? mp_merge(kt, Ak, na, Bk, nb, Sk, stream)
+                         : mp_merge_kv(kt, vt, Ak, Av, na, Bk, Bv, nb, Sk, Sv, stream);
+  };
+  return autotune(kOpMerge, reps, (hipStream_t)stream, run, [] {}, best);
+}
+
+mp_status mp_autotune_batched(mp_dtype kt, const void *A, const int64_t *a_off, const void *B,
+                              const int64_t *b_off, int64_t n_pairs, int64_t total_a,
+                              int64_t total_b, void *S, int reps, mp_config *best, void *stream) {
+  if (!best) return fail(MP_ERR_INVALID_ARG, "mp_autotune_batched: NULL result");
+  auto run = [&]() {
+    return mp_merge_batched(kt, A, a_off, B, b_off, n_pairs, total_a, total_b, S, nullptr, 0,
+                            stream);
+  };
+  return autotune(kOpBatched, reps, (hipStream_t)stream, run, [] {}, best);
+}
+
+mp_status mp_autotune_sort(mp_dtype kt, mp_dtype vt, const void *keys_in, const void *vals_in,
+                           void *keys, void *vals, int64_t n, void *ws, size_t ws_bytes, int reps,
+                           mp_config *best, void *stream) {
+  if (!best) return fail(MP_ERR_INVALID_ARG, "mp_autotune_sort: NULL result");
+  const size_t es = dtype_size(kt);
+  if (es == 0 || n < 0 || (n > 0 && (!keys_in || !keys)) || (vt != MP_NONE && n > 0 && (!vals_in || !vals)))
+    return fail(MP_ERR_INVALID_ARG, "mp_autotune_sort: bad arguments");
+  if (overlaps(span(keys_in, n, es), span(keys, n, es)))
+    return fail(MP_ERR_OVERLAP, "mp_autotune_sort: source and work keys overlap");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t copy_err = hipSuccess;
+  auto setup = [&]() {
+    if (copy_err == hipSuccess && n > 0)
+      copy_err = hipMemcpyAsync(keys, keys_in, (size_t)n * es, hipMemcpyDeviceToDevice, s);
+    if (copy_err == hipSuccess && n > 0 && vt != MP_NONE)
+      copy_err = hipMemcpyAsync(vals, vals_in, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+  };
+  auto run = [&]() {
+    if (copy_err != hipSuccess) return hip_fail(copy_err, "mp_autotune_sort: restoring input");
+    return mp_sort(kt, vt, keys, vals, n, ws, ws_bytes, stream);
+  };
+  return autotune(kOpSort, reps, s, run, setup, best);
+}
+
+mp_status mp_get_config(const char *op, mp_config *cfg) {
+  const int i = op_index(op);
+  if (i < 0 || !cfg) return fail(MP_ERR_INVALID_ARG, "mp_get_config: unknown operation or NULL");
+  *cfg = g_config[i];
+  return MP_OK;
 }
 
 }  // extern "C"

@@ -5,6 +5,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
+#include <vector>
+
 #include "mergepath.h"
 
 namespace mp {
@@ -104,6 +107,12 @@ class KernelTimer {
   hipStream_t s_;
   hipEvent_t start_ = nullptr;
 };
+
+// Graph mode (mp_graph_enable): issue(stream) is recorded once per key into a
+// hipGraph and replayed on s; otherwise issue(s) runs directly.
+bool graph_mode();
+hipError_t run_maybe_graph(std::vector<uint64_t> key, hipStream_t s,
+                           const std::function<hipError_t(hipStream_t)> &issue);
 
 // Record the message returned by mp_last_error() (this thread) and return st.
 mp_status set_error(mp_status st, const char *fmt, ...);

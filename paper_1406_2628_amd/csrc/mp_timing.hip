@@ -52,6 +52,9 @@ unsigned long long *stats_device_ptr() {
 
 KernelTimer::KernelTimer(const char *name, hipStream_t s) : name_(name), s_(s) {
   if (!g_on.load(std::memory_order_relaxed)) return;
+  // kernels recorded into a graph are not timed (no event nodes in graphs)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   if (hipEventCreate(&start_) != hipSuccess) {
     start_ = nullptr;
     return;
