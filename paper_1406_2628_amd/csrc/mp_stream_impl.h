@@ -39,6 +39,8 @@
 // return a range end, and a range end that is a truncated edge is rejected.)
 // The next tile's windows are fetched into registers as soon as the end
 // split is known, overlapping their latency with this tile's merge.
+#pragma once
+
 #include "mp_device.h"
 #include "mp_internal.h"
 
@@ -530,13 +532,22 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     __syncthreads();
 
     bool staged = false;
-    if constexpr ((VT * sizeof(K)) % 16 == 0) {
+    // full tile: each lane's VT outputs with the widest LDS store that
+    // divides its run (16 or 8 bytes)
+    constexpr int RUN_BYTES = VT * (int)sizeof(K);
+    constexpr int SW = RUN_BYTES % 16 == 0 ? 16 : (RUN_BYTES % 8 == 0 ? 8 : 0);
+    if constexpr (SW != 0) {
       if (n == T) {
-        // full tile: each lane's VT outputs as 16-byte LDS stores
+        constexpr int PER = SW / (int)sizeof(K);
 #pragma unroll
-        for (int i = 0; i < VT; i += VEC)
-          *reinterpret_cast<u32x4 *>(keys + tid * VT + i) =
-              *reinterpret_cast<const u32x4 *>(out + i);
+        for (int i = 0; i < VT; i += PER) {
+          if constexpr (SW == 16)
+            *reinterpret_cast<u32x4 *>(keys + tid * VT + i) =
+                *reinterpret_cast<const u32x4 *>(out + i);
+          else
+            *reinterpret_cast<uint2 *>(keys + tid * VT + i) =
+                *reinterpret_cast<const uint2 *>(out + i);
+        }
         if constexpr (KV) {
 #pragma unroll
           for (int i = 0; i < VT; ++i) vals[tid * VT + i] = ov[i];
@@ -646,6 +657,8 @@ static hipError_t launch_pairs(StreamCfg cfg, bool vec, const PairArgs<K> &args,
   MP_PAIRS_CASE(256, 16)
   MP_PAIRS_CASE(256, 8)
   MP_PAIRS_CASE(256, 12)
+  MP_PAIRS_CASE(256, 14)
+  MP_PAIRS_CASE(256, 18)
   MP_PAIRS_CASE(128, 16)
   MP_PAIRS_CASE(512, 8)
 #undef MP_PAIRS_CASE
@@ -698,19 +711,18 @@ hipError_t launch_sort_round(StreamCfg cfg, const K *X, const uint32_t *Xv, K *Y
   return launch_pairs<K, kRuns>(cfg, vec, a, s);
 }
 
-#define MP_INSTANTIATE(K)                                                            \
-  template hipError_t launch_merge_stream<K>(StreamCfg, const K *, const uint32_t *, \
-                                             int64_t, const K *, const uint32_t *,   \
-                                             int64_t, K *, uint32_t *, hipStream_t); \
-  template hipError_t launch_merge_batched<K>(StreamCfg, const K *, const int64_t *, \
-                                              const K *, const int64_t *, int64_t,   \
-                                              int64_t, int64_t, K *, hipStream_t);   \
-  template hipError_t launch_sort_round<K>(StreamCfg, const K *, const uint32_t *,   \
-                                           K *, uint32_t *, int64_t, int, hipStream_t);
-MP_INSTANTIATE(uint32_t)
-MP_INSTANTIATE(int32_t)
-MP_INSTANTIATE(uint64_t)
-MP_INSTANTIATE(float)
-#undef MP_INSTANTIATE
-
 }  // namespace mp
+
+// Each mp_stream_<key>.hip instantiates the launchers for one key type (one
+// translation unit per key type keeps the build parallel).
+#define MP_STREAM_INSTANTIATE(K)                                                         \
+  namespace mp {                                                                         \
+  template hipError_t launch_merge_stream<K>(StreamCfg, const K *, const uint32_t *,     \
+                                             int64_t, const K *, const uint32_t *,       \
+                                             int64_t, K *, uint32_t *, hipStream_t);     \
+  template hipError_t launch_merge_batched<K>(StreamCfg, const K *, const int64_t *,     \
+                                              const K *, const int64_t *, int64_t,       \
+                                              int64_t, int64_t, K *, hipStream_t);       \
+  template hipError_t launch_sort_round<K>(StreamCfg, const K *, const uint32_t *, K *,  \
+                                           uint32_t *, int64_t, int, hipStream_t);       \
+  }
