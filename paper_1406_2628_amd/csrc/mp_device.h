@@ -70,4 +70,30 @@ __device__ __forceinline__ void serial_merge(const K *keys, int ai, int bi,
   }
 }
 
+// The same merge without end tests, for a lane whose run ends at the split
+// (a1, b1) of the next lane's diagonal with A[a1] and B[b1] both real keys in
+// LDS.  Then every compare reads real keys and takes the right side: while
+// the lane still has A keys left, B[b1] >= A[ai] (the split's condition
+// A[a1-1] <= B[b1]); while it has B keys left, B[bi] < A[a1] (the condition
+// B[b1-1] < A[a1]).  So no step needs to know where either input ends.
+template <typename K, int VT>
+__device__ __forceinline__ void serial_merge_inner(const K *keys, int ai, int bi,
+                                                   K (&out)[VT], int (&src)[VT]) {
+  K ka = keys[ai];
+  K kb = keys[bi];
+#pragma unroll
+  for (int i = 0; i < VT; ++i) {
+    const bool take_b = kb < ka;
+    out[i] = take_b ? kb : ka;
+    const int taken = take_b ? bi : ai;
+    src[i] = taken;
+    // the side just taken advances to its next key, which is read next
+    ai = take_b ? ai : taken + 1;
+    bi = take_b ? taken + 1 : bi;
+    const K nxt = keys[taken + 1];
+    ka = take_b ? ka : nxt;
+    kb = take_b ? nxt : kb;
+  }
+}
+
 }  // namespace mp

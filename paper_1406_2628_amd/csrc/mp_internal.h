@@ -95,6 +95,10 @@ hipError_t launch_copy(const void *src, void *dst, int64_t n_bytes, int unroll,
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
+// Workgroup count the last persistent merge launch chose before clipping to
+// its tile count (the autotuner derives grid candidates from it).
+extern int g_last_pairs_grid;
+
 // Brackets one kernel launch with HIP events on its stream while timing is
 // enabled (mp_timing_enable); does nothing otherwise.
 class KernelTimer {

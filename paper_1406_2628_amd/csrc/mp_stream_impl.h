@@ -180,7 +180,7 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   __shared__ __attribute__((aligned(16))) uint32_t vals[KV ? LDS_N : 1];
   __shared__ int64_t t_a[TP + 1], t_b[TP + 1];  // a_off / b_off of pairs [tk, tk + TP]
   __shared__ int64_t s_split, s_kf, s_kl, s_kf2, s_kl2, s_tk;
-  __shared__ int s_end, s_valid, s_pa, s_pb;
+  __shared__ int s_end, s_valid, s_inner, s_pa, s_pb;
 
   const PairArgs<K> &P = args;
   const int tid = threadIdx.x;
@@ -290,23 +290,51 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   };
   K pk[PV][CH];
   uint32_t pv[KV ? PV : 1][CH];
+  // Windows made of whole chunks of directly addressed A' and B' (every
+  // window of a single or batched merge away from the array ends): chunk c
+  // sits at byte c * CH * sizeof(K) from one of two per-window bases, so no
+  // chunk needs 64-bit index arithmetic or a tail test.
+  auto whole_chunks = [&](const Window &w) {
+    return KIND != kRuns && w.fa >= w.ca && w.fb >= w.cb;
+  };
   auto prefetch = [&](const Window &w) {
+    const bool fast = whole_chunks(w);
+    // fast windows: chunk c of A' at ka0 + c * CH, of B' at kb0 + c * CH
+    const K *ka0 = P.A + w.a_base;
+    const K *kb0 = P.B + (w.b_base - (int64_t)w.ca * CH);
+    const uint32_t *va0 = KV ? P.Av + w.a_base : nullptr;
+    const uint32_t *vb0 = KV ? P.Bv + (w.b_base - (int64_t)w.ca * CH) : nullptr;
 #pragma unroll
     for (int k = 0; k < PV; ++k) {
       const int c = tid + k * NT;
       if (c < w.ca + w.cb) {
-        if constexpr (KV) load_chunk(w, c, pk[k], pv[k]);
-        else load_chunk(w, c, pk[k], pv[0]);
+        if (fast) {
+          const bool from_b = c >= w.ca;
+          const uint32_t e = (uint32_t)c * CH;
+          load_chunk_full<K, CH>(from_b ? kb0 : ka0, e, pk[k]);
+          if constexpr (KV) load_chunk_full<uint32_t, CH>(from_b ? vb0 : va0, e, pv[k]);
+        } else {
+          if constexpr (KV) load_chunk(w, c, pk[k], pv[k]);
+          else load_chunk(w, c, pk[k], pv[0]);
+        }
       }
     }
   };
   auto commit = [&](const Window &w) {
+    const bool fast = whole_chunks(w);
+    const int shift_b = OB - w.ca * CH;  // LDS position of chunk c >= ca, minus c * CH
 #pragma unroll
     for (int k = 0; k < PV; ++k) {
       const int c = tid + k * NT;
       if (c < w.ca + w.cb) {
-        if constexpr (KV) put_chunk(w, c, pk[k], pv[k]);
-        else put_chunk(w, c, pk[k], pv[0]);
+        if (fast) {
+          const int pos = c * CH + (c >= w.ca ? shift_b : 0);
+          store_chunk_lds<K, CH>(keys + pos, pk[k]);
+          if constexpr (KV) store_chunk_lds<uint32_t, CH>(vals + pos, pv[k]);
+        } else {
+          if constexpr (KV) put_chunk(w, c, pk[k], pv[k]);
+          else put_chunk(w, c, pk[k], pv[0]);
+        }
       }
     }
   };
@@ -357,13 +385,17 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   // own searches (its own split, at local diagonal 0, is known), then
   // records it here: end split r inside pair k, the window-edge test, the
   // next tile's pair range and the next windows' sizes.
-  auto end_record = [&](const Window &w, int64_t k, int r) {
+  auto end_record = [&](const Window &w, int64_t k, int r, int64_t kt) {
     const int64_t D = d0 + w.n;
     int64_t lo, hi, tlo, thi;
     pair_range(D, k, a_cur, b_cur, w.la, w.lb, lo, hi);
     pair_range(D, k, a_cur, b_cur, w.wa, w.wb, tlo, thi);
     const int64_t ra = a_cur + r;
     s_end = r;
+    // The end split lies strictly inside the loaded windows and before the
+    // ends of the tile's pair: every lane's merge compares real keys of its
+    // own pair only and needs no end tests.
+    s_inner = r < w.la && w.n - r < w.lb && ra < aoff(kt + 1) && D - ra < boff(kt + 1);
     s_valid = lo <= hi && (ra < hi || hi == thi) && (ra > lo || lo == tlo);
     s_kf2 = k;
     const int64_t d1 = D + T < N ? D + T : N;
@@ -447,7 +479,7 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     const int64_t kq_lo = tid == 0 ? kl : kf, kq_hi = tid == 0 ? n_pairs - 1 : kl;
     int64_t k_q;
     int r_q = local_split(w, dq, kq_lo, kq_hi, w.la, w.lb, k_q);
-    if (tid == 0) end_record(w, k_q, r_q);
+    if (tid == 0) end_record(w, k_q, r_q, kf);
     __syncthreads();
     if (!s_valid) {
       // The split left the speculative windows: load the full ones (exact).
@@ -456,12 +488,13 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
       load_now(w);
       __syncthreads();
       r_q = local_split(w, dq, kq_lo, kq_hi, w.la, w.lb, k_q);
-      if (tid == 0) end_record(w, k_q, r_q);
+      if (tid == 0) end_record(w, k_q, r_q, kf);
       __syncthreads();
     }
     const int a_own = tid == 0 ? 0 : r_q;
     const int64_t k_own = tid == 0 ? kf : k_q;
     const int a_end = s_end;
+    const bool inner = s_inner;
     const int64_t a_next = a_cur + a_end, b_next = b_cur + (n - a_end);
     const int64_t kf_next = s_kf2, kl_next = s_kl2;
 
@@ -491,7 +524,8 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
       // enforces it), so a run pair never ends inside a tile.  Batches cross
       // pair ends often: they always take the pair-tracking loop below.
       if (KIND == kSingle || KIND == kRuns) {
-        serial_merge<K, VT>(keys, ai, bi, clip_a(ak1), clip_b(bk1), out, src);
+        if (inner) serial_merge_inner<K, VT>(keys, ai, bi, out, src);
+        else serial_merge<K, VT>(keys, ai, bi, clip_a(ak1), clip_b(bk1), out, src);
       } else {
         // this lane's outputs cross the end of its pair
         // pair end as a tile-local output index (capped past this lane's run)
@@ -572,8 +606,19 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
       const int nvec = n / VEC;
       u32x4 *vdst = reinterpret_cast<u32x4 *>(S + d0);
       const u32x4 *vsrc = reinterpret_cast<const u32x4 *>(keys);
-      for (int v = tid; v < nvec; v += NT) __builtin_nontemporal_store(vsrc[v], vdst + v);
-      for (int i = nvec * VEC + tid; i < n; i += NT) S[d0 + i] = keys[i];
+      if (n == T) {
+        // full tile: a fixed count of vectors per lane, all LDS reads issued
+        // before the first store
+        constexpr int KVN = T / VEC, NK = (KVN + NT - 1) / NT;
+#pragma unroll
+        for (int j = 0; j < NK; ++j) {
+          const int v = tid + j * NT;
+          if (KVN % NT == 0 || v < KVN) __builtin_nontemporal_store(vsrc[v], vdst + v);
+        }
+      } else {
+        for (int v = tid; v < nvec; v += NT) __builtin_nontemporal_store(vsrc[v], vdst + v);
+        for (int i = nvec * VEC + tid; i < n; i += NT) S[d0 + i] = keys[i];
+      }
       if constexpr (KV) {
         const int nv4 = n / 4;
         u32x4 *vd = reinterpret_cast<u32x4 *>(Sv + d0);
@@ -632,6 +677,7 @@ static hipError_t launch_pairs_impl(int grid, bool vec, PairArgs<K> args, hipStr
     }
     grid = per_cu * device_cu_count();
   }
+  g_last_pairs_grid = grid;
   // default prediction margin: about four standard deviations of the change
   // in the A/B mix between consecutive tiles for independent uniform keys
   // (sqrt(T / 2)), plus slack
