@@ -220,6 +220,17 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     else if constexpr (KIND == kRuns) { const int64_t v = k << P.lw; return v < NB ? v : NB; }
     else return (uint64_t)(k - tk) <= (uint64_t)TP ? t_b[k - tk] : P.b_off[k];
   };
+  // End of the A' / B' keys a window of a tile inside pair k may hold.  A
+  // merge-sort round never crosses a pair end inside a tile, so its windows
+  // stop at the pair's ends and stay contiguous in the source array.
+  auto end_a = [&](int64_t k) -> int64_t {
+    if constexpr (KIND == kRuns) return aoff(k + 1);
+    else return NA;
+  };
+  auto end_b = [&](int64_t k) -> int64_t {
+    if constexpr (KIND == kRuns) return boff(k + 1);
+    else return NB;
+  };
   // Last pair k in [klo, khi] with out(k) <= D (out(klo) <= D is required).
   auto pair_of_out = [&](int64_t D, int64_t klo, int64_t khi) -> int64_t {
     if constexpr (KIND == kSingle) return 0;
@@ -290,20 +301,19 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   };
   K pk[PV][CH];
   uint32_t pv[KV ? PV : 1][CH];
-  // Windows made of whole chunks of directly addressed A' and B' (every
-  // window of a single or batched merge away from the array ends): chunk c
-  // sits at byte c * CH * sizeof(K) from one of two per-window bases, so no
-  // chunk needs 64-bit index arithmetic or a tail test.
-  auto whole_chunks = [&](const Window &w) {
-    return KIND != kRuns && w.fa >= w.ca && w.fb >= w.cb;
-  };
+  // Windows made of whole chunks (every window away from the array ends,
+  // and for sort rounds away from the pair ends): both windows are contiguous
+  // in memory, so chunk c sits at c * CH elements from one of two per-window
+  // bases and no chunk needs 64-bit index arithmetic or a tail test.
+  auto whole_chunks = [&](const Window &w) { return w.fa >= w.ca && w.fb >= w.cb; };
   auto prefetch = [&](const Window &w) {
     const bool fast = whole_chunks(w);
     // fast windows: chunk c of A' at ka0 + c * CH, of B' at kb0 + c * CH
-    const K *ka0 = P.A + w.a_base;
-    const K *kb0 = P.B + (w.b_base - (int64_t)w.ca * CH);
-    const uint32_t *va0 = KV ? P.Av + w.a_base : nullptr;
-    const uint32_t *vb0 = KV ? P.Bv + (w.b_base - (int64_t)w.ca * CH) : nullptr;
+    const int64_t xa = a_addr(w.a_base), xb = b_addr(w.b_base) - (int64_t)w.ca * CH;
+    const K *ka0 = P.A + xa;
+    const K *kb0 = P.B + xb;
+    const uint32_t *va0 = KV ? P.Av + xa : nullptr;
+    const uint32_t *vb0 = KV ? P.Bv + xb : nullptr;
 #pragma unroll
     for (int k = 0; k < PV; ++k) {
       const int c = tid + k * NT;
@@ -465,7 +475,7 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     load_table(tk);
   }
   const int n0 = (int)(N - d0 < T ? N - d0 : T);
-  Window w = make_window<CH>(a_cur, b_cur, NA, NB, n0, n0, n0);
+  Window w = make_window<CH>(a_cur, b_cur, end_a(kf), end_b(kf), n0, n0, n0);
   load_now(w);
   __syncthreads();
 
@@ -484,7 +494,7 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     if (!s_valid) {
       // The split left the speculative windows: load the full ones (exact).
       ++n_reload;
-      w = make_window<CH>(a_cur, b_cur, NA, NB, n, n, n);
+      w = make_window<CH>(a_cur, b_cur, end_a(kf), end_b(kf), n, n, n);
       load_now(w);
       __syncthreads();
       r_q = local_split(w, dq, kq_lo, kq_hi, w.la, w.lb, k_q);
@@ -506,7 +516,7 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
       const int n1 = (int)(N - d1 < T ? N - d1 : T);
       const int pa = speculate ? s_pa : n1;
       const int pb = speculate ? s_pb : n1;
-      wn = make_window<CH>(a_next, b_next, NA, NB, n1, pa, pb);
+      wn = make_window<CH>(a_next, b_next, end_a(kf_next), end_b(kf_next), n1, pa, pb);
       if (speculate) prefetch(wn);
     }
 
