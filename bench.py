@@ -260,7 +260,7 @@ def leg_sort(args, ex):
         mp.set_config("sort", None)
         got = dk.cpu().numpy()
         del d0, dk, ws
-        rounds = int(np.ceil(np.log2(max(1, n / 2048))))
+        rounds = int(np.ceil(np.log2(max(1, n / mp.sort_block_keys()))))
         bytes_ = (1 + rounds) * n * 8
         res[name] = {"n": n, "ms": round(ms, 4), "Gkeys_s": round(n / ms / 1e6, 3),
                      "passes": 1 + rounds,

@@ -339,6 +339,8 @@ static size_t sort_ws_keys_bytes(size_t es, int64_t n) {
   return ((size_t)n * es + 255) & ~(size_t)255;
 }
 
+int64_t mp_sort_block_keys(void) { return kSortBlock; }
+
 size_t mp_sort_workspace_bytes(mp_dtype kt, mp_dtype vt, int64_t n) {
   const size_t es = dtype_size(kt);
   if (es == 0 || n <= 0 || (vt != MP_NONE && !is_val32(vt))) return 0;

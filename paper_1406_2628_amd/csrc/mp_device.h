@@ -61,10 +61,12 @@ __device__ __forceinline__ void serial_merge(const K *keys, int ai, int bi,
   for (int i = 0; i < VT; ++i) {
     const bool take_b = (bi < b_end) && (ai >= a_end || kb < ka);
     out[i] = take_b ? kb : ka;
-    src[i] = take_b ? bi : ai;
-    ai += take_b ? 0 : 1;
-    bi += take_b ? 1 : 0;
-    const K nxt = keys[take_b ? bi : ai];
+    const int taken = take_b ? bi : ai;
+    src[i] = taken;
+    // the side just taken advances to its next key, which is read next
+    ai = take_b ? ai : taken + 1;
+    bi = take_b ? taken + 1 : bi;
+    const K nxt = keys[taken + 1];
     ka = take_b ? ka : nxt;
     kb = take_b ? nxt : kb;
   }

@@ -82,7 +82,7 @@ hipError_t launch_sort_round(StreamCfg cfg, const K *X, const uint32_t *Xv, K *Y
                              uint32_t *Yv, int64_t n, int lw, hipStream_t s);
 
 // Stable sort of each block of kSortBlock keys (in place allowed: in == out).
-constexpr int kSortBlockLog2 = 11;
+constexpr int kSortBlockLog2 = 12;
 constexpr int kSortBlock = 1 << kSortBlockLog2;
 template <typename K>
 hipError_t launch_blocksort(const K *in, const uint32_t *vin, K *out, uint32_t *vout,

@@ -529,9 +529,9 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
       auto clip_a = [&](int64_t e) { const int64_t l = e - a_cur; return w.sa + (int)(l < w.la ? l : w.la); };
       auto clip_b = [&](int64_t e) { const int64_t l = e - b_cur; return OB + w.sb + (int)(l < w.lb ? l : w.lb); };
       int ai = w.sa + a_own, bi = OB + w.sb + (dl - a_own);
-      // Run pairs span 2w >= 2 * 2048 outputs and start at multiples of 2w,
-      // and sort tiles are powers of two no larger than 4096 (the host
-      // enforces it), so a run pair never ends inside a tile.  Batches cross
+      // Run pairs span 2w outputs (w at least one sorted block) and start at
+      // multiples of 2w, and sort tiles are powers of two no larger than two
+      // blocks (the host enforces it), so a run pair never ends inside a tile.  Batches cross
       // pair ends often: they always take the pair-tracking loop below.
       if (KIND == kSingle || KIND == kRuns) {
         if (inner) serial_merge_inner<K, VT>(keys, ai, bi, out, src);

@@ -91,6 +91,8 @@ def test_sort_and_batched_argument_errors(L):
     assert L.mp_sort(MP_U32, MP_NONE, k, None, 100_000, None, 0, None) == WORKSPACE
     need = L.mp_sort_workspace_bytes(MP_U32, MP_U32, 1000)
     assert need >= 1000 * 8
+    blk = L.mp_sort_block_keys()
+    assert blk >= 2048 and blk & (blk - 1) == 0
     assert L.mp_sort(MP_U32, MP_U32, k, None, 1000, ws, need, None) == INVALID
     assert L.mp_sort(MP_U32, MP_NONE, k, P(0x20000), 1000, ws, need, None) == INVALID
     assert L.mp_sort(MP_U32, MP_NONE, k, None, 1000, P(0x10000 + 64), need, None) == OVERLAP

@@ -23,7 +23,8 @@ def mp():
 
 # ------------------------------------------------------------------ sort
 
-@pytest.mark.parametrize("n", [0, 1, 2, 7, 2047, 2048, 2049, 4096, 6145, 100_003, 1 << 20])
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 17, 2047, 2048, 2049, 4095, 4096, 4097, 6145, 8191,
+                               8193, 12_289, 100_003, 1 << 20])
 def test_sort_sizes(mp, orc, n):
     from gpu_util import dev, host, first_mismatch
     keys = gen.unsorted_uniform(n, 100 + n)
@@ -42,7 +43,26 @@ def test_sort_dtypes(mp, orc, dt):
     assert first_mismatch(got, orc.sort(keys)) is None
 
 
-@pytest.mark.parametrize("dt", [gen.U32, gen.F32, gen.U64])
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n", [1000, 4097, 5003])
+def test_sort_largest_keys_in_partial_blocks(mp, orc, dt, n):
+    """The last block pads one lane's registers with the largest key; real
+    keys equal to it (and +inf for floats) must still come out in input
+    order, with their values."""
+    from gpu_util import dev, host, first_mismatch
+    g = np.random.default_rng(n)
+    top = np.inf if dt == gen.F32 else np.iinfo(gen.NP_DTYPE[dt]).max
+    keys = g.integers(0, 50, n).astype(gen.NP_DTYPE[dt])
+    keys[g.random(n) < 0.3] = top
+    vals = np.arange(n, dtype=np.uint32)
+    assert first_mismatch(host(mp.sort(dev(keys))), orc.sort(keys)) is None
+    gk, gv = mp.sort(dev(keys), dev(vals))
+    wk, wv = orc.sort(keys, vals)
+    assert first_mismatch(host(gk), wk) is None
+    assert first_mismatch(host(gv), wv) is None
+
+
+@pytest.mark.parametrize("dt", [gen.U32, gen.I32, gen.F32, gen.U64])
 def test_sort_kv_stable(mp, orc, dt):
     """Values follow keys; equal keys keep their input order (stability)."""
     from gpu_util import dev, host, first_mismatch
