@@ -239,11 +239,19 @@ mp_status mp_lp_load(mp_lp *h, const char *path);
  *                   on-chip memory; Algorithm 3, Theorem 17)
  *         nt, vt: lanes per workgroup and outputs per lane (tile = nt*vt)
  *         grid: workgroups of a persistent launch, 0 = one resident wave
- *         margin: persistent mode only.  Each tile's input windows are
- *               sized from the previous tile's consumption plus `margin`
- *               keys per input, with an exact reload when the split leaves
- *               them.  0 = built-in margin, < 0 = always load full windows
- *               (n keys of each input per tile of n outputs).
+ *         margin: persistent mode only; how each tile's input windows are
+ *               sized (a split found on a truncated window edge always
+ *               triggers an exact reload of full windows):
+ *               0  = predicted as for >0 with a built-in margin; after a
+ *                    window reload, and for as long as the A/B mix stays
+ *                    unpredictable (long runs of equal keys), from a
+ *                    64-point probe of the tile's end split issued a tile
+ *                    ahead (one 65-way step of the Theorem 14 search).
+ *                    Batched merges use the prediction only;
+ *               >0 = from the previous tile's A/B mix plus `margin` keys per
+ *                    input;
+ *               <0 = full windows (n keys of each input per tile of n
+ *                    outputs).
  * Returns MP_ERR_UNSUPPORTED for an (nt, vt) pair that is not compiled in.
  */
 typedef struct {

@@ -39,6 +39,10 @@
 // return a range end, and a range end that is a truncated edge is rejected.)
 // The next tile's windows are fetched into registers as soon as the end
 // split is known, overlapping their latency with this tile's merge.
+// By default the windows are not predicted from the A/B mix (which heavy
+// runs of equal keys upset) but bracketed by probes of the split two tiles
+// ahead (see the lookahead probes below); the mix prediction plus a margin
+// remains for a workgroup's first tile and as an option.
 #pragma once
 
 #include "mp_device.h"
@@ -56,7 +60,7 @@ struct PairArgs {
   uint32_t *Sv;
   int64_t NA, NB;          // lengths of A' and B'
   int64_t n_tiles;
-  int margin;              // < 0: full windows
+  int margin;              // 0: lookahead windows, > 0: predicted + margin, < 0: full
   int lw;                  // kRuns: log2 of the run width
   const int64_t *a_off, *b_off;  // kExplicit
   int64_t n_pairs;
@@ -92,6 +96,14 @@ __device__ int64_t wave_split_search(int64_t d, int64_t lo, int64_t hi, GA ga, G
     }
   }
   return lo;
+}
+
+// Value of the first active lane (wave-uniform).
+__device__ __forceinline__ int64_t first_lane64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // Chunk of CH consecutive elements at src + g, loaded with one vector access.
@@ -179,8 +191,9 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   __shared__ __attribute__((aligned(16))) K keys[LDS_N];
   __shared__ __attribute__((aligned(16))) uint32_t vals[KV ? LDS_N : 1];
   __shared__ int64_t t_a[TP + 1], t_b[TP + 1];  // a_off / b_off of pairs [tk, tk + TP]
-  __shared__ int64_t s_split, s_kf, s_kl, s_kf2, s_kl2, s_tk;
-  __shared__ int s_end, s_valid, s_inner, s_pa, s_pb;
+  __shared__ int64_t s_split, s_kf, s_kl, s_kf2, s_kl2, s_tk, s_pq_D, s_pq_lo;
+  __shared__ int s_pq_span;
+  __shared__ int s_end, s_valid, s_inner, s_pa, s_pb, s_rearm;
 
   const PairArgs<K> &P = args;
   const int tid = threadIdx.x;
@@ -190,8 +203,14 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   const int64_t t_begin = g * P.n_tiles / G;
   const int64_t t_end = (g + 1) * P.n_tiles / G;
   if (t_begin >= t_end) return;
+  // margin == 0: windows sized by the lookahead probes below; > 0: sized by
+  // the predicted end split plus this margin; < 0: full windows
   const bool speculate = P.margin >= 0;
-  const int M = P.margin > MAX_MARGIN ? MAX_MARGIN : P.margin;
+  // (batches keep the prediction: their pair bookkeeping is heavier per
+  // tile and their reloads are rare)
+  const bool lookahead = KIND != kExplicit && P.margin == 0;
+  const int M0 = P.margin > 0 ? P.margin : 64 + T / 32;
+  const int M = M0 > MAX_MARGIN ? MAX_MARGIN : M0;
 
   // ---- addressing of A' and B' -------------------------------------------
   auto a_addr = [&](int64_t i) -> int64_t {
@@ -389,13 +408,12 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     a = a > dl - lb ? a : dl - lb;
     return a > 0 ? a : 0;
   };
-  // End split of the tile and the window-edge test; the next tile's pair
-  // range (lane 0 only).
   // Lane 0 searches the tile's end diagonal in step with the other lanes'
-  // own searches (its own split, at local diagonal 0, is known), then
-  // records it here: end split r inside pair k, the window-edge test, the
-  // next tile's pair range and the next windows' sizes.
-  auto end_record = [&](const Window &w, int64_t k, int r, int64_t kt) {
+  // own searches (its own split, at local diagonal 0, is known) and the
+  // result is recorded here (see record_end): end split r inside pair k, the
+  // window-edge test, the next tile's pair range and the next windows' sizes.
+  auto end_record = [&](const Window &w, int64_t k, int r, int64_t kt, bool have,
+                        int64_t b_lo, int64_t b_hi, int64_t b_D) {
     const int64_t D = d0 + w.n;
     int64_t lo, hi, tlo, thi;
     pair_range(D, k, a_cur, b_cur, w.la, w.lb, lo, hi);
@@ -410,10 +428,14 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     s_kf2 = k;
     const int64_t d1 = D + T < N ? D + T : N;
     s_kl2 = d1 > D ? pair_of_out(d1 - 1, k, n_pairs - 1) : k;
-    // Window sizes for the next tile: predict its end split, then add the
+    // Window sizes for the next tile: predict its end split and add the
     // margin.  Inside the same pair the path keeps this tile's A/B mix; a new
-    // pair starts from its own A fraction.  The pair's candidate interval
-    // caps both windows exactly.
+    // pair starts from its own A fraction.  With a lookahead bracket
+    // [b_lo, b_hi] of that split the windows instead reach just past both
+    // ends of the bracket (the keys at the split itself included), and a
+    // bracket the prediction would not have covered keeps the probes going.
+    // The pair's candidate interval caps both windows exactly.
+    s_rearm = 0;
     if (d1 > D) {
       const int64_t k1 = pair_of_out(d1, s_kl2, n_pairs - 1);
       const int64_t ak = aoff(k1), bk = boff(k1), ak1 = aoff(k1 + 1), bk1 = boff(k1 + 1);
@@ -435,10 +457,73 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
       const int64_t alo = lo1 > a_nx ? lo1 : a_nx;
       const int64_t ahi = hi1 < a_nx + (d1 - D) ? hi1 : a_nx + (d1 - D);
       ap = ap < alo ? alo : (ap > ahi ? ahi : ap);
-      const int64_t pa = ap - a_nx + M, pb = (d1 - ap) - b_nx + M;
+      int64_t pa = ap - a_nx + M, pb = (d1 - ap) - b_nx + M;
+      if (have && b_D == d1) {
+        const int64_t qa = b_hi - a_nx + 1, qb = (d1 - b_lo) - b_nx + 1;
+        s_rearm = qa > pa || qb > pb;
+        pa = qa;
+        pb = qb;
+      }
       s_pa = (int)(pa < hi1 - a_nx ? pa : hi1 - a_nx);
       s_pb = (int)(pb < (d1 - lo1) - b_nx ? pb : (d1 - lo1) - b_nx);
     }
+  };
+
+  // ---- lookahead probes (wave 0) -----------------------------------------
+  // Once a tile's end split is known, wave 0 probes 64 evenly spaced points
+  // of the interval that must hold the split two tiles further on (Theorem
+  // 14's search cut 65 ways, one step of it).  The loads have a whole tile to
+  // arrive; the ballot one tile later brackets that split to 1/65 of the
+  // interval, which sizes those windows so that they always hold it.  The
+  // probed keys lie inside windows fetched soon after.  Probing costs a few
+  // percent where the A/B mix is steady, so it runs only for PROBE_RUN tiles
+  // after a window reload, extended while the brackets show that the
+  // prediction would have missed (long runs of equal keys).
+  // Only the probed keys stay in registers; the probe's diagonal and
+  // interval wait in LDS (written by lane 0, read after a barrier).
+  K pq_a{}, pq_b{};  // this lane's probe keys
+  auto probe_point = [](int64_t lo, int span, int i) {
+    return lo + ((int64_t)(i + 1) * span) / 65;
+  };
+  // Probe the split on diagonal D, knowing the split (a_b, b_b) on diagonal
+  // a_b + b_b <= D and a pair k_from <= the pair of D.
+  auto probe_issue = [&](int64_t D, int64_t k_from, int64_t a_b, int64_t b_b) {
+    const int64_t k = pair_of_out(D, k_from, n_pairs - 1);
+    const int span_d = (int)(D - a_b - b_b);
+    int64_t lo, hi;
+    pair_range(D, k, a_b, b_b, span_d, span_d, lo, hi);
+    const int span = hi > lo ? (int)(hi - lo) : 0;
+    if (tid == 0) {
+      s_pq_D = D;
+      s_pq_lo = lo;
+      s_pq_span = span;
+    }
+    if (span > 0) {
+      const int64_t pt = probe_point(lo, span, tid);
+      pq_a = P.A[a_addr(pt)];
+      pq_b = P.B[b_addr(D - 1 - pt)];
+    }
+  };
+  // Bracket [b_lo, b_hi] of the pending probe's split on diagonal b_D (all
+  // 64 lanes of wave 0); false when no probe is pending.
+  auto probe_bracket = [&](int64_t &b_lo, int64_t &b_hi, int64_t &b_D) -> bool {
+    b_D = s_pq_D;
+    if (b_D < 0) return false;
+    const int64_t lo = s_pq_lo;
+    const int span = s_pq_span;
+    b_lo = lo;
+    b_hi = lo + span;
+    if (span > 0) {
+      const uint64_t m = __ballot(pq_b < pq_a);
+      if (m == 0) {
+        b_lo = probe_point(lo, span, 63) + 1;
+      } else {
+        const int f = __ffsll((long long)m) - 1;
+        b_hi = probe_point(lo, span, f);
+        if (f > 0) b_lo = probe_point(lo, span, f - 1) + 1;
+      }
+    }
+    return true;
   };
 
   // ---- prologue: this workgroup's first split ----------------------------
@@ -478,6 +563,25 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   Window w = make_window<CH>(a_cur, b_cur, end_a(kf), end_b(kf), n0, n0, n0);
   load_now(w);
   __syncthreads();
+  if (tid == 0) s_pq_D = -1;
+  __syncthreads();
+  constexpr int PROBE_RUN = 128;
+  int probe_left = 0;  // tiles that still issue probes (uniform)
+
+  // Lane 0's end split (r, k) into end_record.  Single merges and sort
+  // rounds run it on all of wave 0 with lane 0's values made uniform, which
+  // keeps its arithmetic in scalar registers; batches keep it on lane 0,
+  // where their pair lookups stay vector loads.
+  auto record_end = [&](int r, int64_t k) {
+    if constexpr (KIND == kExplicit) {
+      if (tid == 0) end_record(w, k, r, kf, false, 0, 0, -1);
+    } else if (tid < 64) {
+      int64_t b_lo = 0, b_hi = 0, b_D = -1;
+      const bool have = probe_bracket(b_lo, b_hi, b_D);
+      const int r0 = __builtin_amdgcn_readfirstlane(r);
+      end_record(w, first_lane64(k), r0, kf, have, b_lo, b_hi, b_D);
+    }
+  };
 
   unsigned long long n_reload = 0;
   for (int64_t t = t_begin; t < t_end; ++t) {
@@ -489,8 +593,9 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     const int64_t kq_lo = tid == 0 ? kl : kf, kq_hi = tid == 0 ? n_pairs - 1 : kl;
     int64_t k_q;
     int r_q = local_split(w, dq, kq_lo, kq_hi, w.la, w.lb, k_q);
-    if (tid == 0) end_record(w, k_q, r_q, kf);
+    record_end(r_q, k_q);
     __syncthreads();
+    const bool reloaded = !s_valid;
     if (!s_valid) {
       // The split left the speculative windows: load the full ones (exact).
       ++n_reload;
@@ -498,8 +603,12 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
       load_now(w);
       __syncthreads();
       r_q = local_split(w, dq, kq_lo, kq_hi, w.la, w.lb, k_q);
-      if (tid == 0) end_record(w, k_q, r_q, kf);
+      record_end(r_q, k_q);
       __syncthreads();
+    }
+    if (lookahead) {
+      if (reloaded || s_rearm) probe_left = PROBE_RUN;
+      else if (probe_left > 0) --probe_left;
     }
     const int a_own = tid == 0 ? 0 : r_q;
     const int64_t k_own = tid == 0 ? kf : k_q;
@@ -507,6 +616,17 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     const bool inner = s_inner;
     const int64_t a_next = a_cur + a_end, b_next = b_cur + (n - a_end);
     const int64_t kf_next = s_kf2, kl_next = s_kl2;
+
+    // Probe the end split of the tile after next (its start, this tile's
+    // end split, is now known).
+    if (lookahead && tid < 64) {
+      if (probe_left > 0 && t + 2 < t_end) {
+        const int64_t D3 = d0 + 3 * T < N ? d0 + 3 * T : N;
+        probe_issue(D3, kf_next, a_next, b_next);
+      } else if (tid == 0) {
+        s_pq_D = -1;
+      }
+    }
 
     // Fetch the next tile's windows while this tile is merged.
     Window wn = w;
@@ -688,10 +808,6 @@ static hipError_t launch_pairs_impl(int grid, bool vec, PairArgs<K> args, hipStr
     grid = per_cu * device_cu_count();
   }
   g_last_pairs_grid = grid;
-  // default prediction margin: about four standard deviations of the change
-  // in the A/B mix between consecutive tiles for independent uniform keys
-  // (sqrt(T / 2)), plus slack
-  if (args.margin == 0) args.margin = 64 + (int)(T / 32);
   const int64_t G = grid < args.n_tiles ? grid : args.n_tiles;
   if (vec)
     hipLaunchKernelGGL((merge_pairs_kernel<K, KV, NT, VT, KIND, true>), dim3((unsigned)G),

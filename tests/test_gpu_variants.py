@@ -68,6 +68,49 @@ def test_speculative_window_margins(mp, orc, margin, vt):
         mp.set_config("merge", None)
 
 
+def _equal_key_runs(n, seed):
+    """Sorted pair made of long runs of few distinct keys: the A/B mix of
+    consecutive tiles flips between all-A and all-B."""
+    g = np.random.default_rng(seed)
+    vals = np.sort(g.choice(1 << 30, 200, replace=False)).astype(np.uint32)
+    w = 1.0 / np.arange(1, 201)  # Zipf(1) masses in random key order
+    g.shuffle(w)
+    p = w / w.sum()
+    A = np.sort(g.choice(vals, n, p=p)).astype(np.uint32)
+    B = np.sort(g.choice(vals, n + 12_345, p=p)).astype(np.uint32)
+    return A, B
+
+
+@pytest.mark.parametrize("kind", ["merge", "sort"])
+def test_lookahead_windows_on_equal_key_runs(mp, orc, kind):
+    """The default window sizing switches to lookahead probes once the
+    prediction misses: same bits as the oracle, and far fewer window reloads
+    than prediction alone (margin > 0)."""
+    from gpu_util import dev, host, first_mismatch
+    A, B = _equal_key_runs(600_000, 5)
+    reloads = {}
+    for margin in (0, 64):
+        # a small grid: every workgroup walks dozens of tiles
+        mp.set_config(kind, 2, 256, 16, 8, margin)
+        try:
+            mp.timing_enable(True)
+            if kind == "merge":
+                got = host(mp.merge(dev(A), dev(B)))
+                want = orc.merge(A, B)
+            else:
+                keys = np.concatenate([A, B])
+                np.random.default_rng(9).shuffle(keys)
+                got = host(mp.sort(dev(keys)))
+                want = orc.sort(keys)
+            reloads[margin] = mp.stats_query()[1]
+            mp.timing_enable(False)
+        finally:
+            mp.set_config(kind, None)
+        assert first_mismatch(got, want) is None, margin
+    assert reloads[64] > 50, reloads
+    assert reloads[0] * 4 < reloads[64], reloads
+
+
 def test_unaligned_views(mp, orc):
     """Sub-array views whose base is not 16-byte aligned take the element-wise path."""
     import torch
