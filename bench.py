@@ -327,8 +327,11 @@ def leg_learned(args, ex):
     del sets
     log("bench: learned: calibrating on a held-out full-size pair (seed 59)")
     A, B = gen.f32_mixture_pair_torch(n, n, 59)
-    res["max_val_err"] = lp.calibrate(A, B, 1 << 16)
-    res["window"] = lp.window
+    res["max_val_err"] = lp.calibrate(A, B, 1 << 20)
+    w = lp.windows()
+    res["window_max"] = lp.window
+    res["window_median"] = int(np.median(w)) if len(w) else lp.window
+    res["window_buckets"] = int(len(w))
     del A, B
     torch.cuda.empty_cache()
     log("bench: learned: timing on the evaluation pair (seed 60)")

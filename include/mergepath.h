@@ -176,9 +176,15 @@ mp_status mp_lp_shape(mp_lp h, int *features, int *hidden);
    (set also clears the Adam moments and step count). */
 mp_status mp_lp_get_params(mp_lp h, float *host, int n);
 mp_status mp_lp_set_params(mp_lp h, const float *host, int n);
-/* Search window half-width w (>= 0); mp_lp_calibrate sets it. */
+/* Search window half-width.  mp_lp_set_window sets one window w (>= 0) for
+   every diagonal; mp_lp_calibrate sets one per bucket of t (1024 equal
+   buckets of [0, 1]).  mp_lp_window returns the largest window (-1 when
+   unset); mp_lp_windows copies up to cap per-bucket windows to HOST memory
+   and returns how many buckets the model has (0: one window everywhere;
+   -1: NULL handle). */
 mp_status mp_lp_set_window(mp_lp h, int64_t window);
-int64_t mp_lp_window(mp_lp h); /* -1 when unset */
+int64_t mp_lp_window(mp_lp h);
+int32_t mp_lp_windows(mp_lp h, int64_t *windows, int32_t cap);
 
 /* Training examples for K stratified diagonals of one (A, B) set: the exact
    splits from the plain search, features X (K x F, device float) and
@@ -207,9 +213,11 @@ mp_status mp_lp_train(mp_lp h, mp_dtype kt, const void *const *As,
                       const int64_t *nas, const void *const *Bs,
                       const int64_t *nbs, int n_sets, int64_t k_diag, int epochs,
                       float lr, float *final_loss, void *stream);
-/* Set the window from a held-out set: the largest |prediction - split| over
-   n_diag stratified diagonals, plus a quarter, plus one.  max_err (HOST, may
-   be NULL) receives that largest error.  Synchronises the stream. */
+/* Set the windows from a held-out set: n_diag random diagonals get exact
+   splits; the window of each t bucket is the largest |prediction - split|
+   seen in the bucket and its two neighbours (the overall largest for a
+   bucket without samples), plus a quarter, plus one.  max_err (HOST, may be
+   NULL) receives the overall largest error.  Synchronises the stream. */
 mp_status mp_lp_calibrate(mp_lp h, mp_dtype kt, const void *A, int64_t na,
                           const void *B, int64_t nb, int64_t n_diag,
                           int64_t *max_err, void *stream);
@@ -220,8 +228,9 @@ mp_status mp_partition_learned(mp_lp h, mp_dtype kt, const void *A, int64_t na,
                                const void *B, int64_t nb, const int64_t *diag,
                                int64_t n_diag, int64_t *a_split,
                                uint64_t *n_fallback, void *stream);
-/* Save / load the model (features, hidden units, window, seed, parameters)
-   in a small binary file; load creates a new handle on the current device. */
+/* Save / load the model (features, hidden units, windows, seed, parameters)
+   in a small binary file; load creates a new handle on the current device
+   and also reads files written before per-bucket windows existed. */
 mp_status mp_lp_save(mp_lp h, const char *path);
 mp_status mp_lp_load(mp_lp *h, const char *path);
 

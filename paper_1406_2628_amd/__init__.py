@@ -77,6 +77,7 @@ def _declare(L):
         "mp_lp_set_params": ([p, p, i32], i32),
         "mp_lp_set_window": ([p, i64], i32),
         "mp_lp_window": ([p], i64),
+        "mp_lp_windows": ([p, ctypes.POINTER(ctypes.c_int64), i32], i32),
         "mp_lp_examples": ([p, i32, p, i64, p, i64, i64, ctypes.c_uint64, p, p, p, p, p], i32),
         "mp_lp_forward": ([p, p, i64, p, p], i32),
         "mp_lp_grad": ([p, p, p, i64, p, p, p], i32),
@@ -303,6 +304,15 @@ class LearnedPartitioner:
     @window.setter
     def window(self, w: int):
         _check(lib().mp_lp_set_window(self._h, w))
+
+    def windows(self):
+        """Per-bucket windows (numpy int64), or an empty array for one window."""
+        import numpy as np
+        n = lib().mp_lp_windows(self._h, None, 0)
+        out = np.zeros(max(n, 0), dtype=np.int64)
+        if n > 0:
+            lib().mp_lp_windows(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n)
+        return out
 
     def get_params(self):
         import numpy as np

@@ -21,7 +21,16 @@
 // minimises the mean squared error of y against (a* - a_prior) / na over
 // exact splits a* produced by the binary search itself; gradients are
 // reduced in a fixed order (deterministic), and Adam updates the weights.
+//
+// Windows.  The model's error is far from uniform along the diagonals (it
+// peaks where the key distribution has a kink: a narrow cluster, a run of
+// equal keys), so calibration keeps one window per bucket of t = d / N
+// (kLpBuckets equal buckets): the largest error measured in the bucket and
+// its two neighbours, with a quarter more room.  A diagonal searches only its
+// bucket's window; a split beyond it is caught by the certificate below and
+// found by the fallback, so the output never depends on the windows.
 #include <math.h>
+#include <algorithm>
 #include <mutex>
 #include <stdio.h>
 #include <string.h>
@@ -36,6 +45,13 @@ namespace mp {
 constexpr int kLpMaxHidden = 64;
 constexpr int kLpMaxFeatures = 5;
 constexpr int kLpMaxParams = kLpMaxHidden * kLpMaxFeatures + 2 * kLpMaxHidden + 1;
+constexpr int kLpBuckets = 1024;  // window buckets of t = d / N
+
+// Bucket of diagonal d in [0, N] (N = na + nb).
+__host__ __device__ inline int lp_bucket(int64_t d, int64_t N) {
+  const int64_t b = N > 0 ? (d * kLpBuckets) / (N + 1) : 0;
+  return (int)(b < 0 ? 0 : (b >= kLpBuckets ? kLpBuckets - 1 : b));
+}
 
 __host__ __device__ inline int lp_num_params(int F, int H) { return H * F + 2 * H + 1; }
 
@@ -215,7 +231,8 @@ __global__ void lp_forward_kernel(const float *__restrict__ params, const float 
   y[k] = lp_forward(sp, x, F, H);
 }
 
-// Largest |a_hat - a*| over a set of diagonals.
+// Largest |a_hat - a*| over a set of diagonals, overall (max_err[0]) and per
+// window bucket (max_err[1 + b]).
 __global__ void lp_error_kernel(const float *__restrict__ params, const int64_t *__restrict__ diag,
                                 const int64_t *__restrict__ split, int64_t K, int64_t na,
                                 int64_t nb, int F, int H, unsigned long long *__restrict__ max_err) {
@@ -237,18 +254,25 @@ __global__ void lp_error_kernel(const float *__restrict__ params, const int64_t 
     err = na + nb;  // a useless prediction: the window must cover the diagonal
   }
   atomicMax(max_err, (unsigned long long)err);
+  atomicMax(max_err + 1 + lp_bucket(diag[k], na + nb), (unsigned long long)err);
 }
 
 // ---- inference: predicted window + exact search + certificate ------------
 
+// windows: kLpBuckets per-bucket windows (device), or NULL for `window`
+// on every diagonal.
 template <typename K>
 __global__ __launch_bounds__(256) void learned_partition_kernel(
-    const float *__restrict__ params, int F, int H, int64_t window, const K *__restrict__ A,
-    int64_t na, const K *__restrict__ B, int64_t nb, const int64_t *__restrict__ diag,
-    int64_t n_diag, int64_t *__restrict__ a_split, unsigned long long *__restrict__ n_fallback) {
+    const float *__restrict__ params, int F, int H, int64_t window,
+    const int64_t *__restrict__ windows, const K *__restrict__ A, int64_t na,
+    const K *__restrict__ B, int64_t nb, const int64_t *__restrict__ diag, int64_t n_diag,
+    int64_t *__restrict__ a_split, unsigned long long *__restrict__ n_fallback) {
   __shared__ float sp[kLpMaxParams];
+  __shared__ int64_t sw[kLpBuckets];
   const int P = lp_num_params(F, H);
   for (int i = threadIdx.x; i < P; i += blockDim.x) sp[i] = params[i];
+  if (windows)
+    for (int i = threadIdx.x; i < kLpBuckets; i += blockDim.x) sw[i] = windows[i];
   __syncthreads();
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_diag) return;
@@ -266,6 +290,7 @@ __global__ __launch_bounds__(256) void learned_partition_kernel(
   int64_t ahat = lp_prior(d, na, nb) +
                  (isfinite(ys) && fabsf(ys) < 4.0e18f ? (int64_t)llrintf(ys) : 0);
   ahat = ahat < dlo ? dlo : (ahat > dhi ? dhi : ahat);
+  if (windows) window = sw[lp_bucket(d, n)];
   int64_t lo = ahat - window > dlo ? ahat - window : dlo;
   int64_t hi = ahat + window < dhi ? ahat + window : dhi;
   auto ga = [&](int64_t i) { return A[i]; };
@@ -309,11 +334,14 @@ struct mp_lp_s {
   int F = 5, H = 32;
   int device = 0;
   uint64_t seed = 0;
-  int64_t window = -1;  // < 0: not calibrated
+  int64_t window = -1;  // largest window; < 0: not calibrated
+  std::vector<int64_t> windows;  // kLpBuckets per-bucket windows, or empty (one window)
+  int64_t *d_windows = nullptr;  // device copy of `windows`
   int64_t step = 0;     // Adam steps taken
   float *params = nullptr, *m = nullptr, *v = nullptr;  // device
   mp::LpBuf X, r, diag, split, gpart, lpart, misc;
   ~mp_lp_s() {
+    if (d_windows) (void)hipFree(d_windows);
     if (params) (void)hipFree(params);
     if (m) (void)hipFree(m);
     if (v) (void)hipFree(v);
@@ -391,6 +419,28 @@ mp_status lp_exact_splits(mp_lp h, mp_dtype kt, const void *A, int64_t na, const
 
 bool lp_valid_key(mp_dtype t) { return t == MP_U32 || t == MP_I32 || t == MP_U64 || t == MP_F32; }
 
+// Install per-bucket windows (empty: one window `w` everywhere).
+mp_status lp_install_windows(mp_lp h, const std::vector<int64_t> &w, int64_t one) {
+  if (w.empty()) {
+    h->windows.clear();
+    h->window = one;
+    return MP_OK;
+  }
+  if (!h->d_windows) {
+    hipError_t e = hipMalloc(&h->d_windows, kLpBuckets * sizeof(int64_t));
+    if (e != hipSuccess) {
+      h->d_windows = nullptr;
+      return lp_hip(e, "window table");
+    }
+  }
+  hipError_t e = hipMemcpy(h->d_windows, w.data(), kLpBuckets * sizeof(int64_t),
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) return lp_hip(e, "window table");
+  h->windows = w;
+  h->window = *std::max_element(w.begin(), w.end());
+  return MP_OK;
+}
+
 }  // namespace
 }  // namespace mp
 
@@ -458,11 +508,17 @@ mp_status mp_lp_set_params(mp_lp h, const float *host, int n) {
 
 mp_status mp_lp_set_window(mp_lp h, int64_t window) {
   if (!h || window < 0) return lp_fail(MP_ERR_INVALID_ARG, "mp_lp_set_window: bad handle or window");
-  h->window = window;
-  return MP_OK;
+  return lp_install_windows(h, {}, window);
 }
 
 int64_t mp_lp_window(mp_lp h) { return h ? h->window : -1; }
+
+int32_t mp_lp_windows(mp_lp h, int64_t *windows, int32_t cap) {
+  if (!h) return -1;
+  if (windows)
+    for (int32_t i = 0; i < cap && i < (int32_t)h->windows.size(); ++i) windows[i] = h->windows[i];
+  return (int32_t)h->windows.size();
+}
 
 mp_status mp_lp_forward(mp_lp h, const float *X, int64_t K, float *y, void *stream) {
   if (!h || K < 0 || (K > 0 && (!X || !y))) return lp_fail(MP_ERR_INVALID_ARG, "mp_lp_forward: bad arguments");
@@ -558,24 +614,40 @@ mp_status mp_lp_calibrate(mp_lp h, mp_dtype kt, const void *A, int64_t na, const
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = h->diag.ensure(n_diag * 8);
   if (e == hipSuccess) e = h->split.ensure(n_diag * 8);
-  if (e == hipSuccess) e = h->misc.ensure(64 * sizeof(float) + kLpMaxParams * sizeof(float));
+  if (e == hipSuccess) e = h->misc.ensure((1 + kLpBuckets) * sizeof(unsigned long long));
   if (e != hipSuccess) return lp_hip(e, "mp_lp_calibrate buffers");
   mp_status st = lp_exact_splits(h, kt, A, na, B, nb, n_diag, h->seed ^ 0xC0FFEEull, 0, s);
   if (st != MP_OK) return st;
   unsigned long long *dmax = (unsigned long long *)h->misc.p;
-  e = hipMemsetAsync(dmax, 0, sizeof(unsigned long long), s);
+  e = hipMemsetAsync(dmax, 0, (1 + kLpBuckets) * sizeof(unsigned long long), s);
   if (e != hipSuccess) return lp_hip(e, "mp_lp_calibrate");
   hipLaunchKernelGGL(lp_error_kernel, dim3((unsigned)((n_diag + 255) / 256)), dim3(256), 0, s,
                      h->params, (const int64_t *)h->diag.p, (const int64_t *)h->split.p, n_diag,
                      na, nb, h->F, h->H, dmax);
-  unsigned long long hm = 0;
-  e = hipMemcpyAsync(&hm, dmax, sizeof hm, hipMemcpyDeviceToHost, s);
+  std::vector<unsigned long long> hm(1 + kLpBuckets);
+  e = hipMemcpyAsync(hm.data(), dmax, hm.size() * sizeof(unsigned long long),
+                     hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return lp_hip(e, "mp_lp_calibrate");
-  // window: the largest validation error with a quarter more room
-  h->window = (int64_t)hm + (int64_t)(hm / 4) + 1;
-  if (max_err) *max_err = (int64_t)hm;
-  return MP_OK;
+  // Per bucket: the largest error seen in the bucket and its neighbours (a
+  // bucket without samples takes the overall largest), with a quarter more
+  // room.  Diagonals between the sampled ones can err more; the certificate
+  // catches those.
+  std::vector<int64_t> w(kLpBuckets);
+  const int64_t all = (int64_t)hm[0];
+  for (int b = 0; b < kLpBuckets; ++b) {
+    int64_t m = 0;
+    bool seen = false;
+    for (int c = b - 1; c <= b + 1; ++c) {
+      if (c < 0 || c >= kLpBuckets) continue;
+      m = std::max(m, (int64_t)hm[1 + c]);
+      seen = seen || hm[1 + c] > 0;
+    }
+    if (!seen) m = all;
+    w[b] = m + m / 4 + 1;
+  }
+  if (max_err) *max_err = all;
+  return lp_install_windows(h, w, 0);
 }
 
 mp_status mp_partition_learned(mp_lp h, mp_dtype kt, const void *A, int64_t na, const void *B,
@@ -593,6 +665,7 @@ mp_status mp_partition_learned(mp_lp h, mp_dtype kt, const void *A, int64_t na, 
     using KT = decltype(k);
     hipLaunchKernelGGL((learned_partition_kernel<KT>), dim3((unsigned)((n_diag + 255) / 256)),
                        dim3(256), 0, s, (const float *)h->params, h->F, h->H, h->window,
+                       h->windows.empty() ? nullptr : (const int64_t *)h->d_windows,
                        (const KT *)A, na, (const KT *)B, nb, diag, n_diag, a_split,
                        (unsigned long long *)n_fallback);
   });
@@ -600,8 +673,10 @@ mp_status mp_partition_learned(mp_lp h, mp_dtype kt, const void *A, int64_t na, 
   return e == hipSuccess ? MP_OK : lp_hip(e, "mp_partition_learned launch");
 }
 
-// File format (little endian): "MPLP" magic, u32 version 1, i32 F, i32 H,
-// i64 window, u64 seed, then F*H + 2H + 1 float32 parameters.
+// File format (little endian): "MPLP" magic, u32 version, i32 F, i32 H,
+// i64 window, u64 seed, then F*H + 2H + 1 float32 parameters; version 2
+// appends i32 n and n i64 per-bucket windows (n = 0 or kLpBuckets).
+// Version 1 files (one window) still load.
 mp_status mp_lp_save(mp_lp h, const char *path) {
   if (!h || !path) return lp_fail(MP_ERR_INVALID_ARG, "mp_lp_save: bad arguments");
   const int P = lp_num_params(h->F, h->H);
@@ -610,11 +685,13 @@ mp_status mp_lp_save(mp_lp h, const char *path) {
   if (e != hipSuccess) return lp_hip(e, "mp_lp_save");
   FILE *f = fopen(path, "wb");
   if (!f) return lp_fail(MP_ERR_INVALID_ARG, "mp_lp_save: cannot open file");
-  const uint32_t ver = 1;
+  const uint32_t ver = 2;
+  const int32_t nw = (int32_t)h->windows.size();
   bool ok = fwrite("MPLP", 1, 4, f) == 4 && fwrite(&ver, 4, 1, f) == 1 &&
             fwrite(&h->F, 4, 1, f) == 1 && fwrite(&h->H, 4, 1, f) == 1 &&
             fwrite(&h->window, 8, 1, f) == 1 && fwrite(&h->seed, 8, 1, f) == 1 &&
-            fwrite(p.data(), sizeof(float), P, f) == (size_t)P;
+            fwrite(p.data(), sizeof(float), P, f) == (size_t)P && fwrite(&nw, 4, 1, f) == 1 &&
+            (nw == 0 || fwrite(h->windows.data(), 8, nw, f) == (size_t)nw);
   ok = (fclose(f) == 0) && ok;
   return ok ? MP_OK : lp_fail(MP_ERR_INVALID_ARG, "mp_lp_save: write failed");
 }
@@ -630,13 +707,23 @@ mp_status mp_lp_load(mp_lp *out, const char *path) {
   int64_t window = -1;
   uint64_t seed = 0;
   bool ok = fread(magic, 1, 4, f) == 4 && !memcmp(magic, "MPLP", 4) && fread(&ver, 4, 1, f) == 1 &&
-            ver == 1 && fread(&F, 4, 1, f) == 1 && fread(&H, 4, 1, f) == 1 &&
+            (ver == 1 || ver == 2) && fread(&F, 4, 1, f) == 1 && fread(&H, 4, 1, f) == 1 &&
             fread(&window, 8, 1, f) == 1 && fread(&seed, 8, 1, f) == 1 &&
             (F == 1 || F == 3 || F == 5) && H >= 1 && H <= kLpMaxHidden;
   std::vector<float> p;
+  std::vector<int64_t> wt;
   if (ok) {
     p.resize(lp_num_params(F, H));
     ok = fread(p.data(), sizeof(float), p.size(), f) == p.size();
+  }
+  if (ok && ver == 2) {
+    int32_t nw = -1;
+    ok = fread(&nw, 4, 1, f) == 1 && (nw == 0 || nw == kLpBuckets);
+    if (ok && nw > 0) {
+      wt.resize(nw);
+      ok = fread(wt.data(), 8, nw, f) == (size_t)nw;
+      for (int64_t x : wt) ok = ok && x >= 0;
+    }
   }
   fclose(f);
   if (!ok) return lp_fail(MP_ERR_STATE, "mp_lp_load: not a model file of this format");
@@ -648,7 +735,11 @@ mp_status mp_lp_load(mp_lp *out, const char *path) {
     mp_lp_destroy(h);
     return st;
   }
-  h->window = window;
+  st = lp_install_windows(h, wt, window);
+  if (st != MP_OK) {
+    mp_lp_destroy(h);
+    return st;
+  }
   *out = h;
   return MP_OK;
 }

@@ -117,6 +117,9 @@ def test_training_reduces_loss(trained):
     assert loss < 0.2 * loss0
     assert lp.window == err + err // 4 + 1
     assert err < n // 4
+    # one window per bucket of t: the largest is the overall one
+    w = lp.windows()
+    assert len(w) == 1024 and w.min() >= 1 and w.max() == lp.window
 
 
 def _check_identical(mp, orc, lp, A, B, diag, expect_fallback=None):
@@ -144,16 +147,16 @@ def test_learned_partition_identical(mp, orc, trained):
     _check_identical(mp, orc, lp, A, B, diag)
 
 
-def test_forced_fallback_zero_window(mp, orc, trained):
+def test_forced_fallback_zero_window(mp, orc, trained, tmp_path):
     lp, _, _, _, n = trained
-    w = lp.window
-    try:
-        lp.window = 0
-        A, B = gen.f32_mixture_pair(n, n, 60)
-        diag = np.random.default_rng(4).integers(0, 2 * n + 1, 5000).astype(np.int64)
-        _check_identical(mp, orc, lp, A, B, diag, expect_fallback=True)
-    finally:
-        lp.window = w
+    path = str(tmp_path / "copy.mplp")
+    lp.save(path)
+    lp0 = mp.LearnedPartitioner.load(path)
+    lp0.window = 0  # one zero-width window everywhere
+    assert len(lp0.windows()) == 0 and lp0.window == 0
+    A, B = gen.f32_mixture_pair(n, n, 60)
+    diag = np.random.default_rng(4).integers(0, 2 * n + 1, 5000).astype(np.int64)
+    _check_identical(mp, orc, lp0, A, B, diag, expect_fallback=True)
 
 
 def test_garbage_model_still_exact(mp, orc):
@@ -177,13 +180,26 @@ def test_other_distribution_and_skew(mp, orc, trained):
         _check_identical(mp, orc, lp, A, B, diag)
 
 
-def test_save_load_roundtrip(mp, trained, tmp_path):
-    lp, _, _, _, _ = trained
+def test_save_load_roundtrip(mp, orc, trained, tmp_path):
+    import struct
+    lp, _, _, _, n = trained
     path = str(tmp_path / "model.mplp")
     lp.save(path)
     lp2 = mp.LearnedPartitioner.load(path)
     assert lp2.shape == lp.shape and lp2.window == lp.window
     assert lp2.get_params().tobytes() == lp.get_params().tobytes()
+    assert np.array_equal(lp2.windows(), lp.windows())
+    # a file of the first format (one window, no table) still loads
+    F_, H_ = lp.shape
+    old = str(tmp_path / "v1.mplp")
+    with open(old, "wb") as f:
+        f.write(b"MPLP" + struct.pack("<Iiiq", 1, F_, H_, 12345) + struct.pack("<Q", 11))
+        f.write(lp.get_params().astype("<f4").tobytes())
+    lp1 = mp.LearnedPartitioner.load(old)
+    assert lp1.window == 12345 and len(lp1.windows()) == 0
+    A, B = gen.f32_mixture_pair(n, n, 61)
+    diag = np.random.default_rng(6).integers(0, 2 * n + 1, 3000).astype(np.int64)
+    _check_identical(mp, orc, lp1, A, B, diag)
     with open(path, "r+b") as f:
         f.write(b"XXXX")
     with pytest.raises(mp.MergePathError, match="STATE"):
