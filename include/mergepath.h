@@ -240,9 +240,9 @@ mp_status mp_lp_load(mp_lp *h, const char *path);
  * it must not be changed while another thread is inside a library call.
  *   op    "merge" (mp_merge and mp_merge_kv), "batched" (mp_merge_batched),
  *         "sort" (the merge rounds of mp_sort)
- *   cfg   NULL restores the built-in choice (persistent, nt 256; merge vt 18,
- *         but vt 12 for 8-byte keys with values; batched and sort vt 16);
- *         otherwise
+ *   cfg   NULL restores the built-in choice (persistent; merge nt 192,
+ *         vt 24, but nt 256, vt 12 for 8-byte keys with values; batched
+ *         and sort nt 256, vt 16); otherwise
  *         mode: 1 = per-tile (one grid split search per output tile, then
  *                   one workgroup per tile; Algorithm 1 with p = tiles),
  *               2 = persistent (each workgroup finds one split and walks a

@@ -54,7 +54,7 @@ enum Op { kOpMerge = 0, kOpBatched = 1, kOpSort = 2, kNumOps = 3 };
 
 // Built-in variant per operation (chosen from measurements on MI355X).
 const mp_config kDefaultConfig[kNumOps] = {
-    {2, 256, 18, 0, 0},  // merge
+    {2, 192, 24, 0, 0},  // merge
     {2, 256, 16, 0, 0},  // batched
     {2, 256, 16, 0, 0},  // sort rounds
 };
@@ -198,10 +198,13 @@ static mp_status merge_common(const char *fn, mp_dtype kt, mp_dtype vt,
   hipStream_t s = (hipStream_t)stream;
   mp_config cfg = current_config(kOpMerge);
   // Built-in choice with values and 8-byte keys: values make a tile's LDS
-  // 1.5 times that of the keys, which at vt 18 leaves one workgroup per
-  // compute unit; vt 12 keeps two (18% faster on 2^27 + 2^27 u64 with
-  // values; with 4-byte keys vt 18 stays best).
-  if (kv && es == 8 && !g_config_chosen[kOpMerge]) cfg.vt = 12;
+  // 1.5 times that of the keys, which at the default tile leaves one
+  // workgroup per compute unit; 256 x 12 keeps two (18% faster on 2^27 +
+  // 2^27 u64 with values).
+  if (kv && es == 8 && !g_config_chosen[kOpMerge]) {
+    cfg.nt = 256;
+    cfg.vt = 12;
+  }
   hipError_t e = hipSuccess;
   if (cfg.mode == 1) {
     const TileCfg tc{cfg.nt, cfg.vt};
@@ -424,8 +427,8 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
 // returns it.  `setup`, when given, runs untimed before every call (the sort
 // restores its unsorted input).
 
-static const int kTuneShapes[][2] = {{256, 16}, {256, 18}, {256, 14}, {256, 12},
-                                     {256, 8},  {128, 16}, {512, 8}};
+static const int kTuneShapes[][2] = {{192, 24}, {256, 16}, {256, 18}, {256, 14},
+                                     {256, 12}, {256, 8},  {128, 16}, {512, 8}};
 
 template <typename Run, typename Setup>
 static mp_status autotune(Op op, int reps, hipStream_t s, Run run, Setup setup, mp_config *best) {

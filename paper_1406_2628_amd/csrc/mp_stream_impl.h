@@ -833,6 +833,7 @@ static hipError_t launch_pairs(StreamCfg cfg, bool vec, const PairArgs<K> &args,
   MP_PAIRS_CASE(256, 18)
   MP_PAIRS_CASE(128, 16)
   MP_PAIRS_CASE(512, 8)
+  MP_PAIRS_CASE(192, 24)
 #undef MP_PAIRS_CASE
   return hipErrorNotSupported;
 }

@@ -8,7 +8,7 @@ pytestmark = pytest.mark.gpu
 
 MERGE_VARIANTS = [(1, 256, 16, 0), (1, 256, 15, 0), (1, 256, 8, 0), (1, 128, 16, 0),
                   (2, 256, 16, 0), (2, 256, 8, 0), (2, 256, 12, 0), (2, 256, 14, 0),
-                  (2, 256, 18, 0), (2, 128, 16, 0),
+                  (2, 256, 18, 0), (2, 128, 16, 0), (2, 192, 24, 0),
                   (2, 512, 8, 0), (2, 256, 16, 7), (2, 256, 16, 1)]
 
 
