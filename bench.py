@@ -329,9 +329,13 @@ def leg_learned(args, ex):
     A, B = gen.f32_mixture_pair_torch(n, n, 59)
     res["max_val_err"] = lp.calibrate(A, B, 1 << 20)
     w = lp.windows()
-    res["window_max"] = lp.window
-    res["window_median"] = int(np.median(w)) if len(w) else lp.window
+    span = (w[:, 1] - w[:, 0]) if len(w) else np.array([2 * lp.window])
     res["window_buckets"] = int(len(w))
+    res["window_span_median"] = int(np.median(span))
+    res["window_span_max"] = int(span.max())
+    # probes of a lower-bound search over a window, averaged over buckets
+    res["mean_window_probes"] = round(float(np.mean(np.ceil(np.log2(span + 1.0)))), 2)
+    res["plain_probes"] = int(np.ceil(np.log2(n + 1.0)))
     del A, B
     torch.cuda.empty_cache()
     log("bench: learned: timing on the evaluation pair (seed 60)")

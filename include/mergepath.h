@@ -150,8 +150,9 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
 /*
  * Learned split predictor.  Not part of the paper: a small FP32 MLP
  * predicts where the Merge Path crosses a diagonal, and the exact search of
- * Algorithm 2 then runs only in a window of +-w around the prediction.  A
- * result on a window edge that is not a diagonal bound is checked against
+ * Algorithm 2 then runs only in a window [a_hat + lo, a_hat + hi] around the
+ * prediction a_hat.  A result on a window edge that is not a diagonal bound
+ * is checked against
  * both conditions of Algorithm 2; if they fail, the full-range search runs.
  * mp_partition_learned therefore always returns exactly what mp_partition
  * returns; the model only changes how many probes that takes.
@@ -176,12 +177,13 @@ mp_status mp_lp_shape(mp_lp h, int *features, int *hidden);
    (set also clears the Adam moments and step count). */
 mp_status mp_lp_get_params(mp_lp h, float *host, int n);
 mp_status mp_lp_set_params(mp_lp h, const float *host, int n);
-/* Search window half-width.  mp_lp_set_window sets one window w (>= 0) for
-   every diagonal; mp_lp_calibrate sets one per bucket of t (1024 equal
-   buckets of [0, 1]).  mp_lp_window returns the largest window (-1 when
-   unset); mp_lp_windows copies up to cap per-bucket windows to HOST memory
-   and returns how many buckets the model has (0: one window everywhere;
-   -1: NULL handle). */
+/* Search windows.  mp_lp_set_window sets the symmetric window [-w, w]
+   (w >= 0) for every diagonal; mp_lp_calibrate sets one asymmetric window
+   (lo, hi offsets from the prediction, lo <= hi) per bucket of t (16384
+   equal buckets of [0, 1]).  mp_lp_window returns the largest |offset| of
+   any window (-1 when unset).  mp_lp_windows copies up to cap buckets'
+   (lo, hi) pairs (2 cap int64) to HOST memory and returns how many buckets
+   the model has (0: one symmetric window everywhere; -1: NULL handle). */
 mp_status mp_lp_set_window(mp_lp h, int64_t window);
 int64_t mp_lp_window(mp_lp h);
 int32_t mp_lp_windows(mp_lp h, int64_t *windows, int32_t cap);
@@ -214,10 +216,13 @@ mp_status mp_lp_train(mp_lp h, mp_dtype kt, const void *const *As,
                       const int64_t *nbs, int n_sets, int64_t k_diag, int epochs,
                       float lr, float *final_loss, void *stream);
 /* Set the windows from a held-out set: n_diag random diagonals get exact
-   splits; the window of each t bucket is the largest |prediction - split|
-   seen in the bucket and its two neighbours (the overall largest for a
-   bucket without samples), plus a quarter, plus one.  max_err (HOST, may be
-   NULL) receives the overall largest error.  Synchronises the stream. */
+   splits and signed errors e = split - prediction.  Bucket b takes the
+   smallest and largest e over buckets [b - r, b + r] (r = max(1,
+   ceil(16 * 16384 / n_diag)); the overall extremes if none of them has a
+   sample), each side widened by an eighth of that span plus
+   ceil(3 sqrt(na nb / (4 (na + nb)))) + 1 (three standard deviations of
+   the seed-to-seed noise of a split of iid samples).  max_err (HOST, may be
+   NULL) receives the largest |e|.  Synchronises the stream. */
 mp_status mp_lp_calibrate(mp_lp h, mp_dtype kt, const void *A, int64_t na,
                           const void *B, int64_t nb, int64_t n_diag,
                           int64_t *max_err, void *stream);
@@ -230,7 +235,8 @@ mp_status mp_partition_learned(mp_lp h, mp_dtype kt, const void *A, int64_t na,
                                uint64_t *n_fallback, void *stream);
 /* Save / load the model (features, hidden units, windows, seed, parameters)
    in a small binary file; load creates a new handle on the current device
-   and also reads files written before per-bucket windows existed. */
+   and also reads the two earlier formats (one window; 1024 symmetric
+   per-bucket windows). */
 mp_status mp_lp_save(mp_lp h, const char *path);
 mp_status mp_lp_load(mp_lp *h, const char *path);
 

@@ -306,10 +306,11 @@ class LearnedPartitioner:
         _check(lib().mp_lp_set_window(self._h, w))
 
     def windows(self):
-        """Per-bucket windows (numpy int64), or an empty array for one window."""
+        """Per-bucket (lo, hi) window offsets as an (n, 2) int64 numpy array,
+        or an empty (0, 2) array when one symmetric window is set."""
         import numpy as np
         n = lib().mp_lp_windows(self._h, None, 0)
-        out = np.zeros(max(n, 0), dtype=np.int64)
+        out = np.zeros((max(n, 0), 2), dtype=np.int64)
         if n > 0:
             lib().mp_lp_windows(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n)
         return out

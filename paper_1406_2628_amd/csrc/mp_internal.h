@@ -62,7 +62,8 @@ struct StreamCfg {
   int nt;
   int vt;
   int grid;
-  int margin;  // speculative window margin: 0 = default, < 0 = full windows
+  int margin;  // window margin: 0 = adaptive (prediction, then lookahead probes),
+               // > 0 = prediction with this margin only, < 0 = full windows
 };
 
 template <typename K>

@@ -24,11 +24,14 @@
 //
 // Windows.  The model's error is far from uniform along the diagonals (it
 // peaks where the key distribution has a kink: a narrow cluster, a run of
-// equal keys), so calibration keeps one window per bucket of t = d / N
-// (kLpBuckets equal buckets): the largest error measured in the bucket and
-// its two neighbours, with a quarter more room.  A diagonal searches only its
-// bucket's window; a split beyond it is caught by the certificate below and
-// found by the fallback, so the output never depends on the windows.
+// equal keys) and, where the smooth model misses such a kink, it is biased
+// to one side.  So calibration keeps, per bucket of t = d / N (kLpBuckets
+// equal buckets), an asymmetric window [a_hat + lo, a_hat + hi]: the
+// smallest and largest signed error a* - a_hat seen in the bucket and its
+// neighbours, widened by an eighth of that span and by three standard
+// deviations of the seed-to-seed noise of a split.  A diagonal searches only
+// its bucket's window; a split beyond it is caught by the certificate below
+// and found by the fallback, so the output never depends on the windows.
 #include <math.h>
 #include <algorithm>
 #include <mutex>
@@ -45,9 +48,12 @@ namespace mp {
 constexpr int kLpMaxHidden = 64;
 constexpr int kLpMaxFeatures = 5;
 constexpr int kLpMaxParams = kLpMaxHidden * kLpMaxFeatures + 2 * kLpMaxHidden + 1;
-constexpr int kLpBuckets = 1024;  // window buckets of t = d / N
+constexpr int kLpBuckets = 16384;  // window buckets of t = d / N
+constexpr int kLpOldBuckets = 1024;  // buckets of the symmetric windows of format 2
+static_assert(kLpBuckets % kLpOldBuckets == 0, "format 2 buckets must nest");
 
-// Bucket of diagonal d in [0, N] (N = na + nb).
+// Bucket of diagonal d in [0, N] (N = na + nb): floor(d K / (N + 1)), exact
+// for N < 2^49 (any pair that fits in device memory).
 __host__ __device__ inline int lp_bucket(int64_t d, int64_t N) {
   const int64_t b = N > 0 ? (d * kLpBuckets) / (N + 1) : 0;
   return (int)(b < 0 ? 0 : (b >= kLpBuckets ? kLpBuckets - 1 : b));
@@ -91,6 +97,26 @@ __device__ __forceinline__ float lp_forward(const PP &p, const float *x, int F, 
     y = fmaf(p[ow2 + j], z > 0.f ? z : 0.f, y);
   }
   return y;
+}
+
+// Prediction for diagonal d clipped to the diagonal [dlo, dhi]: the point
+// both calibration and search put their windows around.  A prediction that
+// is not finite (or absurdly large) adds nothing to the prior.
+template <typename PP>
+__device__ __forceinline__ int64_t lp_predict(const PP &p, int64_t d, int64_t na, int64_t nb,
+                                              int F, int H, int64_t dlo, int64_t dhi) {
+  float x[kLpMaxFeatures];
+  lp_features(d, na, nb, F, x);
+  const float ys = lp_forward(p, x, F, H) * (float)na;
+  const int64_t a = lp_prior(d, na, nb) +
+                    (isfinite(ys) && fabsf(ys) < 4.0e18f ? (int64_t)llrintf(ys) : 0);
+  return a < dlo ? dlo : (a > dhi ? dhi : a);
+}
+
+// a_hat + off clipped to [dlo, dhi], without overflow for any offset
+// (dlo <= a_hat <= dhi).
+__device__ __forceinline__ int64_t lp_edge(int64_t ahat, int64_t off, int64_t dlo, int64_t dhi) {
+  return off <= dlo - ahat ? dlo : (off >= dhi - ahat ? dhi : ahat + off);
 }
 
 // ---- training kernels -------------------------------------------------------
@@ -233,34 +259,38 @@ __global__ void lp_forward_kernel(const float *__restrict__ params, const float 
 
 // Largest |a_hat - a*| over a set of diagonals, overall (max_err[0]) and per
 // window bucket (max_err[1 + b]).
+// Signed calibration errors e = a* - a_hat.  err[0]: the largest |e|; per
+// bucket b, err[1 + b] the smallest and err[1 + kLpBuckets + b] the largest
+// e, each stored as e with its sign bit flipped so that unsigned atomics
+// order them as signed values (the caller fills the minima with all ones
+// and the maxima with zeros).
+__device__ __forceinline__ unsigned long long lp_ordered(int64_t e) {
+  return (unsigned long long)e ^ (1ull << 63);
+}
+
 __global__ void lp_error_kernel(const float *__restrict__ params, const int64_t *__restrict__ diag,
                                 const int64_t *__restrict__ split, int64_t K, int64_t na,
-                                int64_t nb, int F, int H, unsigned long long *__restrict__ max_err) {
+                                int64_t nb, int F, int H, unsigned long long *__restrict__ err) {
   __shared__ float sp[kLpMaxParams];
   const int P = lp_num_params(F, H);
   for (int i = threadIdx.x; i < P; i += blockDim.x) sp[i] = params[i];
   __syncthreads();
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
-  float x[kLpMaxFeatures];
-  lp_features(diag[k], na, nb, F, x);
-  const float y = lp_forward(sp, x, F, H);
-  const float ys = y * (float)na;
-  int64_t err;
-  if (isfinite(ys) && fabsf(ys) < 4.0e18f) {
-    const int64_t ahat = lp_prior(diag[k], na, nb) + (int64_t)llrintf(ys);
-    err = ahat > split[k] ? ahat - split[k] : split[k] - ahat;
-  } else {
-    err = na + nb;  // a useless prediction: the window must cover the diagonal
-  }
-  atomicMax(max_err, (unsigned long long)err);
-  atomicMax(max_err + 1 + lp_bucket(diag[k], na + nb), (unsigned long long)err);
+  const int64_t d = diag[k];
+  int64_t dlo, dhi;
+  diag_range<int64_t>(d, na, nb, dlo, dhi);
+  const int64_t e = split[k] - lp_predict(sp, d, na, nb, F, H, dlo, dhi);
+  const int b = lp_bucket(d, na + nb);
+  atomicMax(err, (unsigned long long)(e < 0 ? -e : e));
+  atomicMin(err + 1 + b, lp_ordered(e));
+  atomicMax(err + 1 + kLpBuckets + b, lp_ordered(e));
 }
 
 // ---- inference: predicted window + exact search + certificate ------------
 
-// windows: kLpBuckets per-bucket windows (device), or NULL for `window`
-// on every diagonal.
+// windows: kLpBuckets (lo, hi) offset pairs (device), or NULL for the
+// symmetric window [-window, window] on every diagonal.
 template <typename K>
 __global__ __launch_bounds__(256) void learned_partition_kernel(
     const float *__restrict__ params, int F, int H, int64_t window,
@@ -268,11 +298,8 @@ __global__ __launch_bounds__(256) void learned_partition_kernel(
     const K *__restrict__ B, int64_t nb, const int64_t *__restrict__ diag, int64_t n_diag,
     int64_t *__restrict__ a_split, unsigned long long *__restrict__ n_fallback) {
   __shared__ float sp[kLpMaxParams];
-  __shared__ int64_t sw[kLpBuckets];
   const int P = lp_num_params(F, H);
   for (int i = threadIdx.x; i < P; i += blockDim.x) sp[i] = params[i];
-  if (windows)
-    for (int i = threadIdx.x; i < kLpBuckets; i += blockDim.x) sw[i] = windows[i];
   __syncthreads();
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_diag) return;
@@ -281,18 +308,17 @@ __global__ __launch_bounds__(256) void learned_partition_kernel(
   d = d < 0 ? 0 : (d > n ? n : d);
   int64_t dlo, dhi;
   diag_range<int64_t>(d, na, nb, dlo, dhi);
-  float x[kLpMaxFeatures];
-  lp_features(d, na, nb, F, x);
-  const float y = lp_forward(sp, x, F, H);
-  const float ys = y * (float)na;
-  // a prediction outside the diagonal (or not finite) still gives a valid
-  // window after clipping
-  int64_t ahat = lp_prior(d, na, nb) +
-                 (isfinite(ys) && fabsf(ys) < 4.0e18f ? (int64_t)llrintf(ys) : 0);
-  ahat = ahat < dlo ? dlo : (ahat > dhi ? dhi : ahat);
-  if (windows) window = sw[lp_bucket(d, n)];
-  int64_t lo = ahat - window > dlo ? ahat - window : dlo;
-  int64_t hi = ahat + window < dhi ? ahat + window : dhi;
+  // the window offsets depend on d alone: their load overlaps the model
+  int64_t wlo = -window, whi = window;
+  if (windows) {
+    const int b = lp_bucket(d, n);
+    wlo = windows[2 * b];
+    whi = windows[2 * b + 1];
+  }
+  const int64_t ahat = lp_predict(sp, d, na, nb, F, H, dlo, dhi);
+  // wlo <= whi, so lo <= hi
+  const int64_t lo = lp_edge(ahat, wlo, dlo, dhi);
+  const int64_t hi = lp_edge(ahat, whi, dlo, dhi);
   auto ga = [&](int64_t i) { return A[i]; };
   auto gb = [&](int64_t j) { return B[j]; };
   int64_t a = split_search<int64_t>(d, lo, hi, ga, gb);
@@ -334,8 +360,9 @@ struct mp_lp_s {
   int F = 5, H = 32;
   int device = 0;
   uint64_t seed = 0;
-  int64_t window = -1;  // largest window; < 0: not calibrated
-  std::vector<int64_t> windows;  // kLpBuckets per-bucket windows, or empty (one window)
+  int64_t window = -1;  // largest |offset| of any window; < 0: not calibrated
+  // kLpBuckets (lo, hi) offset pairs, or empty ([-window, window] everywhere)
+  std::vector<int64_t> windows;
   int64_t *d_windows = nullptr;  // device copy of `windows`
   int64_t step = 0;     // Adam steps taken
   float *params = nullptr, *m = nullptr, *v = nullptr;  // device
@@ -419,7 +446,8 @@ mp_status lp_exact_splits(mp_lp h, mp_dtype kt, const void *A, int64_t na, const
 
 bool lp_valid_key(mp_dtype t) { return t == MP_U32 || t == MP_I32 || t == MP_U64 || t == MP_F32; }
 
-// Install per-bucket windows (empty: one window `w` everywhere).
+// Install per-bucket windows (w: kLpBuckets (lo, hi) pairs with lo <= hi),
+// or, for an empty w, the window [-one, one] everywhere.
 mp_status lp_install_windows(mp_lp h, const std::vector<int64_t> &w, int64_t one) {
   if (w.empty()) {
     h->windows.clear();
@@ -427,17 +455,19 @@ mp_status lp_install_windows(mp_lp h, const std::vector<int64_t> &w, int64_t one
     return MP_OK;
   }
   if (!h->d_windows) {
-    hipError_t e = hipMalloc(&h->d_windows, kLpBuckets * sizeof(int64_t));
+    hipError_t e = hipMalloc(&h->d_windows, 2 * kLpBuckets * sizeof(int64_t));
     if (e != hipSuccess) {
       h->d_windows = nullptr;
       return lp_hip(e, "window table");
     }
   }
-  hipError_t e = hipMemcpy(h->d_windows, w.data(), kLpBuckets * sizeof(int64_t),
+  hipError_t e = hipMemcpy(h->d_windows, w.data(), 2 * kLpBuckets * sizeof(int64_t),
                            hipMemcpyHostToDevice);
   if (e != hipSuccess) return lp_hip(e, "window table");
   h->windows = w;
-  h->window = *std::max_element(w.begin(), w.end());
+  int64_t m = 0;
+  for (int64_t x : w) m = std::max(m, x < 0 ? -x : x);
+  h->window = m;
   return MP_OK;
 }
 
@@ -515,9 +545,10 @@ int64_t mp_lp_window(mp_lp h) { return h ? h->window : -1; }
 
 int32_t mp_lp_windows(mp_lp h, int64_t *windows, int32_t cap) {
   if (!h) return -1;
+  const int32_t n = (int32_t)(h->windows.size() / 2);
   if (windows)
-    for (int32_t i = 0; i < cap && i < (int32_t)h->windows.size(); ++i) windows[i] = h->windows[i];
-  return (int32_t)h->windows.size();
+    for (int32_t i = 0; i < 2 * cap && i < 2 * n; ++i) windows[i] = h->windows[i];
+  return n;
 }
 
 mp_status mp_lp_forward(mp_lp h, const float *X, int64_t K, float *y, void *stream) {
@@ -612,41 +643,93 @@ mp_status mp_lp_calibrate(mp_lp h, mp_dtype kt, const void *A, int64_t na, const
   if (!h || !lp_valid_key(kt) || na < 0 || nb < 0 || n_diag <= 0 || (na && !A) || (nb && !B))
     return lp_fail(MP_ERR_INVALID_ARG, "mp_lp_calibrate: bad arguments");
   hipStream_t s = (hipStream_t)stream;
+  const size_t n_err = 1 + 2 * (size_t)kLpBuckets;
   hipError_t e = h->diag.ensure(n_diag * 8);
   if (e == hipSuccess) e = h->split.ensure(n_diag * 8);
-  if (e == hipSuccess) e = h->misc.ensure((1 + kLpBuckets) * sizeof(unsigned long long));
+  if (e == hipSuccess) e = h->misc.ensure(n_err * sizeof(unsigned long long));
   if (e != hipSuccess) return lp_hip(e, "mp_lp_calibrate buffers");
   mp_status st = lp_exact_splits(h, kt, A, na, B, nb, n_diag, h->seed ^ 0xC0FFEEull, 0, s);
   if (st != MP_OK) return st;
-  unsigned long long *dmax = (unsigned long long *)h->misc.p;
-  e = hipMemsetAsync(dmax, 0, (1 + kLpBuckets) * sizeof(unsigned long long), s);
+  unsigned long long *derr = (unsigned long long *)h->misc.p;
+  e = hipMemsetAsync(derr, 0, sizeof(unsigned long long), s);
+  if (e == hipSuccess) e = hipMemsetAsync(derr + 1, 0xff, kLpBuckets * sizeof(unsigned long long), s);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(derr + 1 + kLpBuckets, 0, kLpBuckets * sizeof(unsigned long long), s);
   if (e != hipSuccess) return lp_hip(e, "mp_lp_calibrate");
   hipLaunchKernelGGL(lp_error_kernel, dim3((unsigned)((n_diag + 255) / 256)), dim3(256), 0, s,
                      h->params, (const int64_t *)h->diag.p, (const int64_t *)h->split.p, n_diag,
-                     na, nb, h->F, h->H, dmax);
-  std::vector<unsigned long long> hm(1 + kLpBuckets);
-  e = hipMemcpyAsync(hm.data(), dmax, hm.size() * sizeof(unsigned long long),
-                     hipMemcpyDeviceToHost, s);
+                     na, nb, h->F, h->H, derr);
+  std::vector<unsigned long long> he(n_err);
+  e = hipMemcpyAsync(he.data(), derr, n_err * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return lp_hip(e, "mp_lp_calibrate");
-  // Per bucket: the largest error seen in the bucket and its neighbours (a
-  // bucket without samples takes the overall largest), with a quarter more
-  // room.  Diagonals between the sampled ones can err more; the certificate
-  // catches those.
-  std::vector<int64_t> w(kLpBuckets);
-  const int64_t all = (int64_t)hm[0];
+  auto signed_of = [](unsigned long long u) { return (int64_t)(u ^ (1ull << 63)); };
+  const unsigned long long kEmpty = ~0ull;  // a minimum slot no sample reached
+  // Overall extremes, for buckets without samples nearby.
+  int64_t all_lo = 0, all_hi = 0;
+  bool any = false;
   for (int b = 0; b < kLpBuckets; ++b) {
-    int64_t m = 0;
-    bool seen = false;
-    for (int c = b - 1; c <= b + 1; ++c) {
-      if (c < 0 || c >= kLpBuckets) continue;
-      m = std::max(m, (int64_t)hm[1 + c]);
-      seen = seen || hm[1 + c] > 0;
-    }
-    if (!seen) m = all;
-    w[b] = m + m / 4 + 1;
+    if (he[1 + b] == kEmpty) continue;
+    const int64_t lo = signed_of(he[1 + b]), hi = signed_of(he[1 + kLpBuckets + b]);
+    all_lo = any ? std::min(all_lo, lo) : lo;
+    all_hi = any ? std::max(all_hi, hi) : hi;
+    any = true;
   }
-  if (max_err) *max_err = all;
+  // Neighbourhood of a bucket: itself and r buckets on each side, r chosen
+  // so that it holds about 16 samples or more (r = 1 at 16 samples per
+  // bucket).
+  const int64_t r64 = (16 * (int64_t)kLpBuckets + n_diag - 1) / n_diag;
+  const int r = (int)std::min<int64_t>(std::max<int64_t>(r64, 1), kLpBuckets);
+  // Seed-to-seed noise of a split: for two iid samples the number of A keys
+  // among the first d keys of the merge is hypergeometric, with variance at
+  // most na nb / (4 (na + nb)).
+  const double sigma = na + nb > 0 ? sqrt((double)na * (double)nb / (4.0 * (double)(na + nb))) : 0.0;
+  const int64_t noise = (int64_t)ceil(3.0 * sigma) + 1;
+  // Extremes over [b - r, b + r] for every b in O(kLpBuckets) (van Herk /
+  // Gil-Werman: running extremes inside blocks of 2r + 1, from the left and
+  // from the right); an empty bucket holds the neutral value.
+  const int64_t kNone = INT64_MAX;  // neutral for the minimum; -kNone for the maximum
+  auto sliding = [&](std::vector<int64_t> v, bool is_max) {
+    const int K = kLpBuckets, m = 2 * r + 1;
+    auto pick = [&](int64_t a, int64_t b) { return is_max ? std::max(a, b) : std::min(a, b); };
+    // pre/suf: extremes from the start of i's block to i / from i to the
+    // end of its block; p0/s0: from bucket 0 to i / from i to the last.
+    std::vector<int64_t> pre(K), suf(K), p0(K), s0(K), out(K);
+    for (int i = 0; i < K; ++i) {
+      pre[i] = (i % m == 0) ? v[i] : pick(pre[i - 1], v[i]);
+      p0[i] = i == 0 ? v[i] : pick(p0[i - 1], v[i]);
+    }
+    for (int i = K - 1; i >= 0; --i) {
+      suf[i] = (i % m == m - 1 || i == K - 1) ? v[i] : pick(suf[i + 1], v[i]);
+      s0[i] = i == K - 1 ? v[i] : pick(s0[i + 1], v[i]);
+    }
+    for (int b = 0; b < K; ++b) {
+      const int l = b - r, h = b + r;
+      if (l <= 0)
+        out[b] = p0[h < K - 1 ? h : K - 1];
+      else if (h >= K - 1)
+        out[b] = s0[l];
+      else
+        out[b] = pick(suf[l], pre[h]);  // [l, h] spans one block or two adjacent ones
+    }
+    return out;
+  };
+  std::vector<int64_t> bmin(kLpBuckets), bmax(kLpBuckets);
+  for (int b = 0; b < kLpBuckets; ++b) {
+    const bool has = he[1 + b] != kEmpty;
+    bmin[b] = has ? signed_of(he[1 + b]) : kNone;
+    bmax[b] = has ? signed_of(he[1 + kLpBuckets + b]) : -kNone;
+  }
+  const std::vector<int64_t> nmin = sliding(bmin, false), nmax = sliding(bmax, true);
+  std::vector<int64_t> w(2 * (size_t)kLpBuckets);
+  for (int b = 0; b < kLpBuckets; ++b) {
+    const bool seen = nmin[b] != kNone;
+    const int64_t lo = seen ? nmin[b] : all_lo, hi = seen ? nmax[b] : all_hi;
+    const int64_t pad = (hi - lo) / 8 + noise;
+    w[2 * b] = lo - pad;
+    w[2 * b + 1] = hi + pad;
+  }
+  if (max_err) *max_err = (int64_t)he[0];
   return lp_install_windows(h, w, 0);
 }
 
@@ -674,9 +757,12 @@ mp_status mp_partition_learned(mp_lp h, mp_dtype kt, const void *A, int64_t na, 
 }
 
 // File format (little endian): "MPLP" magic, u32 version, i32 F, i32 H,
-// i64 window, u64 seed, then F*H + 2H + 1 float32 parameters; version 2
-// appends i32 n and n i64 per-bucket windows (n = 0 or kLpBuckets).
-// Version 1 files (one window) still load.
+// i64 window, u64 seed, then F*H + 2H + 1 float32 parameters; version 3
+// appends i32 n and n (lo, hi) i64 offset pairs (n = 0 or kLpBuckets).
+// Older files still load: version 1 has one window, version 2 appends i32 n
+// and n i64 symmetric windows over kLpOldBuckets buckets (each covers
+// kLpBuckets / kLpOldBuckets of today's buckets exactly, since both divide
+// [0, N] the same way).
 mp_status mp_lp_save(mp_lp h, const char *path) {
   if (!h || !path) return lp_fail(MP_ERR_INVALID_ARG, "mp_lp_save: bad arguments");
   const int P = lp_num_params(h->F, h->H);
@@ -685,13 +771,13 @@ mp_status mp_lp_save(mp_lp h, const char *path) {
   if (e != hipSuccess) return lp_hip(e, "mp_lp_save");
   FILE *f = fopen(path, "wb");
   if (!f) return lp_fail(MP_ERR_INVALID_ARG, "mp_lp_save: cannot open file");
-  const uint32_t ver = 2;
-  const int32_t nw = (int32_t)h->windows.size();
+  const uint32_t ver = 3;
+  const int32_t nw = (int32_t)(h->windows.size() / 2);
   bool ok = fwrite("MPLP", 1, 4, f) == 4 && fwrite(&ver, 4, 1, f) == 1 &&
             fwrite(&h->F, 4, 1, f) == 1 && fwrite(&h->H, 4, 1, f) == 1 &&
             fwrite(&h->window, 8, 1, f) == 1 && fwrite(&h->seed, 8, 1, f) == 1 &&
             fwrite(p.data(), sizeof(float), P, f) == (size_t)P && fwrite(&nw, 4, 1, f) == 1 &&
-            (nw == 0 || fwrite(h->windows.data(), 8, nw, f) == (size_t)nw);
+            (nw == 0 || fwrite(h->windows.data(), 8, 2 * (size_t)nw, f) == 2 * (size_t)nw);
   ok = (fclose(f) == 0) && ok;
   return ok ? MP_OK : lp_fail(MP_ERR_INVALID_ARG, "mp_lp_save: write failed");
 }
@@ -707,7 +793,7 @@ mp_status mp_lp_load(mp_lp *out, const char *path) {
   int64_t window = -1;
   uint64_t seed = 0;
   bool ok = fread(magic, 1, 4, f) == 4 && !memcmp(magic, "MPLP", 4) && fread(&ver, 4, 1, f) == 1 &&
-            (ver == 1 || ver == 2) && fread(&F, 4, 1, f) == 1 && fread(&H, 4, 1, f) == 1 &&
+            (ver >= 1 && ver <= 3) && fread(&F, 4, 1, f) == 1 && fread(&H, 4, 1, f) == 1 &&
             fread(&window, 8, 1, f) == 1 && fread(&seed, 8, 1, f) == 1 &&
             (F == 1 || F == 3 || F == 5) && H >= 1 && H <= kLpMaxHidden;
   std::vector<float> p;
@@ -716,14 +802,25 @@ mp_status mp_lp_load(mp_lp *out, const char *path) {
     p.resize(lp_num_params(F, H));
     ok = fread(p.data(), sizeof(float), p.size(), f) == p.size();
   }
-  if (ok && ver == 2) {
-    int32_t nw = -1;
-    ok = fread(&nw, 4, 1, f) == 1 && (nw == 0 || nw == kLpBuckets);
-    if (ok && nw > 0) {
-      wt.resize(nw);
-      ok = fread(wt.data(), 8, nw, f) == (size_t)nw;
-      for (int64_t x : wt) ok = ok && x >= 0;
+  int32_t nw = 0;
+  if (ok && ver >= 2) ok = fread(&nw, 4, 1, f) == 1;
+  if (ok && ver == 2 && nw != 0) {
+    std::vector<int64_t> old(kLpOldBuckets);
+    ok = nw == kLpOldBuckets && fread(old.data(), 8, old.size(), f) == old.size();
+    for (size_t i = 0; ok && i < old.size(); ++i) ok = old[i] >= 0;
+    if (ok) {
+      constexpr int rep = kLpBuckets / kLpOldBuckets;
+      wt.resize(2 * (size_t)kLpBuckets);
+      for (int b = 0; b < kLpBuckets; ++b) {
+        wt[2 * b] = -old[b / rep];
+        wt[2 * b + 1] = old[b / rep];
+      }
     }
+  }
+  if (ok && ver == 3 && nw != 0) {
+    wt.resize(2 * (size_t)kLpBuckets);
+    ok = nw == kLpBuckets && fread(wt.data(), 8, wt.size(), f) == wt.size();
+    for (int b = 0; ok && b < kLpBuckets; ++b) ok = wt[2 * b] <= wt[2 * b + 1];
   }
   fclose(f);
   if (!ok) return lp_fail(MP_ERR_STATE, "mp_lp_load: not a model file of this format");

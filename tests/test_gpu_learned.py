@@ -112,14 +112,59 @@ def trained(mp):
     return lp, loss0, loss, err, n
 
 
+BUCKETS = 16384
+CAL_SEED, CAL_DIAG = 11 ^ 0xC0FFEE, 1 << 14   # the fixture's calibration diagonals
+
+
 def test_training_reduces_loss(trained):
     lp, loss0, loss, err, n = trained
     assert loss < 0.2 * loss0
-    assert lp.window == err + err // 4 + 1
     assert err < n // 4
-    # one window per bucket of t: the largest is the overall one
+    # one (lo, hi) window per bucket of t; lp.window is the largest |offset|
     w = lp.windows()
-    assert len(w) == 1024 and w.min() >= 1 and w.max() == lp.window
+    assert w.shape == (BUCKETS, 2) and np.all(w[:, 0] < w[:, 1])
+    assert lp.window == np.abs(w).max() and lp.window >= err
+
+
+def _calibration_windows_np(e, d, na, nb, n_diag):
+    """The documented calibration rule, written out with a brute-force
+    neighbourhood (the library uses running extremes)."""
+    N = na + nb
+    b = np.minimum(d * BUCKETS // (N + 1), BUCKETS - 1)
+    r = max(1, -(-16 * BUCKETS // n_diag))
+    noise = int(np.ceil(3.0 * np.sqrt(float(na) * float(nb) / (4.0 * float(N))))) + 1
+    w = np.empty((BUCKETS, 2), np.int64)
+    for k in range(BUCKETS):
+        m = (b >= k - r) & (b <= k + r)
+        lo, hi = (e[m].min(), e[m].max()) if m.any() else (e.min(), e.max())
+        pad = (hi - lo) // 8 + noise
+        w[k] = (lo - pad, hi + pad)
+    return w
+
+
+def test_calibration_windows_follow_the_rule(mp, trained):
+    """Rebuild the calibration sample (same diagonals, exact splits, model
+    outputs), apply the documented rule on the host, and compare bit for
+    bit; then every calibration diagonal must be found inside its window."""
+    import torch
+    from gpu_util import dev, host
+    lp, _, _, _, n = trained
+    A, B = gen.f32_mixture_pair(n, n, 59)
+    dA, dB = dev(A), dev(B)
+    X, _, d, s = lp.examples(dA, dB, CAL_DIAG, seed=CAL_SEED)
+    y = host(lp.forward(X))
+    d, s = host(d), host(s)
+    na = nb = n
+    ys = y.astype(np.float32) * np.float32(na)
+    ok = np.isfinite(ys) & (np.abs(ys) < np.float32(4e18))
+    ahat = _prior_np(d, na, nb) + np.where(ok, np.rint(np.where(ok, ys, 0)), 0).astype(np.int64)
+    ahat = np.clip(ahat, np.maximum(0, d - nb), np.minimum(d, na))
+    e = s - ahat
+    assert np.array_equal(lp.windows(), _calibration_windows_np(e, d, na, nb, CAL_DIAG))
+    fb = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    got = host(lp.partition(dA, dB, dev(d), fallbacks=fb))
+    assert np.array_equal(got, s)
+    assert int(fb.cpu().numpy()[0]) == 0
 
 
 def _check_identical(mp, orc, lp, A, B, diag, expect_fallback=None):
@@ -157,6 +202,19 @@ def test_forced_fallback_zero_window(mp, orc, trained, tmp_path):
     A, B = gen.f32_mixture_pair(n, n, 60)
     diag = np.random.default_rng(4).integers(0, 2 * n + 1, 5000).astype(np.int64)
     _check_identical(mp, orc, lp0, A, B, diag, expect_fallback=True)
+
+
+def test_unbounded_window_is_the_full_search(mp, orc, trained, tmp_path):
+    """The largest window offset clips to the diagonal without overflow."""
+    lp, _, _, _, n = trained
+    path = str(tmp_path / "copy.mplp")
+    lp.save(path)
+    big = mp.LearnedPartitioner.load(path)
+    big.window = (1 << 63) - 1
+    A, B = gen.f32_mixture_pair(n, n, 60)
+    diag = np.concatenate([[0, 1, n, 2 * n - 1, 2 * n],
+                           np.random.default_rng(9).integers(0, 2 * n + 1, 4000)]).astype(np.int64)
+    _check_identical(mp, orc, big, A, B, diag, expect_fallback=False)
 
 
 def test_garbage_model_still_exact(mp, orc):
@@ -197,9 +255,22 @@ def test_save_load_roundtrip(mp, orc, trained, tmp_path):
         f.write(lp.get_params().astype("<f4").tobytes())
     lp1 = mp.LearnedPartitioner.load(old)
     assert lp1.window == 12345 and len(lp1.windows()) == 0
+    # the second format: 1024 symmetric per-bucket windows, each covering 16
+    # of today's buckets
+    sym = np.random.default_rng(12).integers(0, 5000, 1024).astype("<i8")
+    v2 = str(tmp_path / "v2.mplp")
+    with open(v2, "wb") as f:
+        f.write(b"MPLP" + struct.pack("<Iiiq", 2, F_, H_, int(sym.max())) + struct.pack("<Q", 11))
+        f.write(lp.get_params().astype("<f4").tobytes())
+        f.write(struct.pack("<i", 1024) + sym.tobytes())
+    lp2w = mp.LearnedPartitioner.load(v2)
+    rep = np.repeat(sym, BUCKETS // 1024)
+    assert np.array_equal(lp2w.windows(), np.stack([-rep, rep], 1))
+    assert lp2w.window == sym.max()
     A, B = gen.f32_mixture_pair(n, n, 61)
     diag = np.random.default_rng(6).integers(0, 2 * n + 1, 3000).astype(np.int64)
     _check_identical(mp, orc, lp1, A, B, diag)
+    _check_identical(mp, orc, lp2w, A, B, diag)
     with open(path, "r+b") as f:
         f.write(b"XXXX")
     with pytest.raises(mp.MergePathError, match="STATE"):
