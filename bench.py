@@ -260,10 +260,11 @@ def leg_sort(args, ex):
         mp.set_config("sort", None)
         got = dk.cpu().numpy()
         del d0, dk, ws
-        rounds = int(np.ceil(np.log2(max(1, n / mp.sort_block_keys()))))
+        block = mp.sort_block_keys(torch.uint32)
+        rounds = int(np.ceil(np.log2(max(1, n / block))))
         bytes_ = (1 + rounds) * n * 8
         res[name] = {"n": n, "ms": round(ms, 4), "Gkeys_s": round(n / ms / 1e6, 3),
-                     "passes": 1 + rounds,
+                     "passes": 1 + rounds, "block_keys": block,
                      "hbm_frac": round(bytes_ / ms / 1e6 / HBM_PEAK_GBS, 4),
                      "blocksort_ms": round(bs[0] / max(1, bs[1]), 4),
                      "round_ms": round(rd[0] / max(1, rd[1]), 4),

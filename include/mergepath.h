@@ -139,10 +139,12 @@ mp_status mp_merge_batched(mp_dtype kt, const void *A, const int64_t *a_off,
  *               permuted with their keys
  *   ws          device workspace of at least mp_sort_workspace_bytes(kt, vt, n)
  * mp_sort_block_keys returns the length of the blocks sorted first (the
- * runs the first merge round starts from): a sort of n keys makes
- * 1 + ceil(log2(n / mp_sort_block_keys())) passes over the data.
+ * runs the first merge round starts from) for keys of dtype kt with values
+ * of dtype vt (MP_NONE: keys only), or 0 for an unsupported pair: a sort of
+ * n keys makes 1 + ceil(log2(n / mp_sort_block_keys(kt, vt))) passes over
+ * the data.
  */
-int64_t mp_sort_block_keys(void);
+int64_t mp_sort_block_keys(mp_dtype kt, mp_dtype vt);
 size_t mp_sort_workspace_bytes(mp_dtype kt, mp_dtype vt, int64_t n);
 mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
                   void *ws, size_t ws_bytes, void *stream);

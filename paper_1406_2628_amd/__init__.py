@@ -52,7 +52,7 @@ def _declare(L):
         "mp_merge_kv": ([i32, i32, p, p, i64, p, p, i64, p, p, p], i32),
         "mp_merge_batched_workspace_bytes": ([i32, i64, i64], sz),
         "mp_merge_batched": ([i32, p, p, p, p, i64, i64, i64, p, p, sz, p], i32),
-        "mp_sort_block_keys": ([], i64),
+        "mp_sort_block_keys": ([ctypes.c_int, ctypes.c_int], i64),
         "mp_sort_workspace_bytes": ([i32, i32, i64], sz),
         "mp_sort": ([i32, i32, p, p, i64, p, sz, p], i32),
         "mp_set_config": ([ctypes.c_char_p, ctypes.c_void_p], i32),
@@ -253,9 +253,11 @@ def merge_batched(A, a_off, B, b_off, total_a: int | None = None, total_b: int |
     return out
 
 
-def sort_block_keys() -> int:
+def sort_block_keys(key_dtype: torch.dtype, val_dtype: torch.dtype | None = None) -> int:
     """Length of the blocks the sort orders first (its first runs)."""
-    return int(lib().mp_sort_block_keys())
+    vt = MP_NONE if val_dtype is None else {torch.uint32: MP_U32, torch.int32: MP_I32,
+                                             torch.float32: MP_F32}[val_dtype]
+    return int(lib().mp_sort_block_keys(TORCH_TO_MP[key_dtype], vt))
 
 
 def sort_workspace_bytes(key_dtype: torch.dtype, val_dtype: torch.dtype | None, n: int) -> int:

@@ -269,9 +269,9 @@ mp_status mp_set_config(const char *op, const mp_config *cfg) {
   if (i == kOpSort) {
     // merge rounds rely on tiles that divide every run pair (2w >= 2 blocks)
     const int64_t t = (int64_t)cfg->nt * cfg->vt;
-    if ((t & (t - 1)) != 0 || t > 2 * kSortBlock)
+    if ((t & (t - 1)) != 0 || t > (2 << kSortBlockMinLog2))
       return fail(MP_ERR_UNSUPPORTED, "mp_set_config: sort tiles must be a power of two <= %d",
-                  2 * kSortBlock);
+                  2 << kSortBlockMinLog2);
   }
   g_config[i] = *cfg;
   g_config_chosen[i] = true;
@@ -352,7 +352,11 @@ static size_t sort_ws_keys_bytes(size_t es, int64_t n) {
   return ((size_t)n * es + 255) & ~(size_t)255;
 }
 
-int64_t mp_sort_block_keys(void) { return kSortBlock; }
+int64_t mp_sort_block_keys(mp_dtype kt, mp_dtype vt) {
+  const size_t es = dtype_size(kt);
+  if (es == 0 || (vt != MP_NONE && !is_val32(vt))) return 0;
+  return (int64_t)1 << sort_block_log2(es, vt != MP_NONE);
+}
 
 size_t mp_sort_workspace_bytes(mp_dtype kt, mp_dtype vt, int64_t n) {
   const size_t es = dtype_size(kt);
@@ -384,8 +388,9 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
   const mp_config cfg = current_config(kOpSort);
   const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
   hipStream_t s = (hipStream_t)stream;
+  const int lb = sort_block_log2(es, kv);
   int rounds = 0;
-  for (int64_t w = kSortBlock; w < n; w <<= 1) ++rounds;
+  for (int64_t w = (int64_t)1 << lb; w < n; w <<= 1) ++rounds;
   const std::vector<uint64_t> key = {
       2, (uint64_t)kt, (uint64_t)vt, (uint64_t)(uintptr_t)keys, (uint64_t)(uintptr_t)vals,
       (uint64_t)n, (uint64_t)(uintptr_t)ws, (uint64_t)cfg.nt, (uint64_t)cfg.vt,
@@ -402,9 +407,10 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
       int cur = rounds % 2;
       {
         KernelTimer timer("blocksort", st);
-        ee = launch_blocksort<K>((const K *)keys, (const uint32_t *)vals, kb[cur], vb[cur], n, st);
+        ee = launch_blocksort<K>((const K *)keys, (const uint32_t *)vals, kb[cur], vb[cur], n, lb,
+                                 st);
       }
-      for (int lw = kSortBlockLog2; ee == hipSuccess && ((int64_t)1 << lw) < n; ++lw) {
+      for (int lw = lb; ee == hipSuccess && ((int64_t)1 << lw) < n; ++lw) {
         KernelTimer timer("sort_round", st);
         ee = launch_sort_round<K>(sc, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, lw, st);
         cur ^= 1;
@@ -479,7 +485,7 @@ static mp_status autotune(Op op, int reps, hipStream_t s, Run run, Setup setup, 
     mp_config c{2, shape[0], shape[1], 0, 0};
     if (op == kOpSort) {
       const int64_t t = (int64_t)c.nt * c.vt;
-      if ((t & (t - 1)) != 0 || t > 2 * kSortBlock) continue;
+      if ((t & (t - 1)) != 0 || t > (2 << kSortBlockMinLog2)) continue;
     }
     g_last_pairs_grid = 0;
     const float ms = time_config(c);

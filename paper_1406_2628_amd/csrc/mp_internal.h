@@ -82,12 +82,16 @@ template <typename K>
 hipError_t launch_sort_round(StreamCfg cfg, const K *X, const uint32_t *Xv, K *Y,
                              uint32_t *Yv, int64_t n, int lw, hipStream_t s);
 
-// Stable sort of each block of kSortBlock keys (in place allowed: in == out).
-constexpr int kSortBlockLog2 = 12;
-constexpr int kSortBlock = 1 << kSortBlockLog2;
+// Stable sort of each block of 2^log2_block keys (in place allowed:
+// in == out).  One workgroup of 2^log2_block / 16 lanes per block;
+// log2_block is kSortBlockMinLog2 .. kSortBlockMaxLog2.
+constexpr int kSortBlockMinLog2 = 12;
+constexpr int kSortBlockMaxLog2 = 14;
+// Block size the sort uses for a key size, with or without 32-bit values.
+int sort_block_log2(size_t key_bytes, bool kv);
 template <typename K>
 hipError_t launch_blocksort(const K *in, const uint32_t *vin, K *out, uint32_t *vout,
-                            int64_t n, hipStream_t s);
+                            int64_t n, int log2_block, hipStream_t s);
 
 // Plain 16-byte streaming copy (bandwidth reference).
 hipError_t launch_copy(const void *src, void *dst, int64_t n_bytes, int unroll,

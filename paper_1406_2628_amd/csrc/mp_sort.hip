@@ -1,11 +1,11 @@
 // Block sort: the first stage of the cache-efficient merge sort (section 4.2:
 // sort blocks sized to on-chip memory, then merge rounds), with LDS as the
-// cache.  One workgroup of 256 lanes sorts a block of 4096 keys:
+// cache.  One workgroup of NT lanes sorts a block of NT * 16 keys:
 //   1. every lane sorts its 16 keys in registers with Batcher's odd-even
 //      merge network.  Where the order of equal keys can be seen (values
 //      travel with the keys, or float keys, whose +0 and -0 compare equal),
 //      the network orders (key, position) pairs, which makes it stable;
-//   2. eight rounds of Merge Path inside LDS merge runs of 16, 32, ..., 2048
+//   2. rounds of Merge Path inside LDS merge runs of 16, 32, ..., NT * 8
 //      keys pairwise: the lanes of a run pair each find their split at local
 //      diagonal q * 16 (Algorithm 2) and merge 16 outputs serially, left run
 //      as A so that ties keep input order (section 2.1 tie rule).  Outputs
@@ -57,12 +57,11 @@ __host__ __device__ constexpr int lds_pos(int i) {
 // in and out may be the same array (each block is read whole before it is
 // written), so they are not declared __restrict__.  vec: all four arrays are
 // 16-byte aligned (full blocks then move as 16-byte vectors).
-template <typename K, bool KV>
-__global__ __launch_bounds__(256) void blocksort_kernel(const K *in, const uint32_t *vin,
-                                                        K *out, uint32_t *vout, int64_t n,
-                                                        int vec) {
-  constexpr int NT = 256, VT = 16, BS = NT * VT;
-  static_assert(BS == kSortBlock, "block size");
+template <typename K, bool KV, int NT>
+__global__ __launch_bounds__(NT) void blocksort_kernel(const K *in, const uint32_t *vin,
+                                                       K *out, uint32_t *vout, int64_t n,
+                                                       int vec) {
+  constexpr int VT = 16, BS = NT * VT;
   constexpr int VEC = 16 / (int)sizeof(K);
   constexpr bool STABLE = KV || std::is_floating_point<K>::value;
   // VT + 1 slack slots for the unguarded steps of the serial merge
@@ -243,25 +242,54 @@ __global__ __launch_bounds__(256) void blocksort_kernel(const K *in, const uint3
   }
 }
 
-template <typename K>
-hipError_t launch_blocksort(const K *in, const uint32_t *vin, K *out, uint32_t *vout,
-                            int64_t n, hipStream_t s) {
-  const int64_t blocks = (n + kSortBlock - 1) / kSortBlock;
+// Larger blocks leave fewer merge rounds in HBM (each reads and writes every
+// key once) for one more round in LDS each.  4-byte keys: 16384-key blocks
+// (1024 lanes; 68 KB of LDS, 135 KB with values).  8-byte keys: 8192 (70 KB,
+// 104 KB with values; 16384 would not fit with values).
+int sort_block_log2(size_t key_bytes, bool kv) {
+  (void)kv;
+  return key_bytes == 8 ? 13 : 14;
+}
+
+template <typename K, bool KV, int NT>
+hipError_t launch_blocksort_nt(const K *in, const uint32_t *vin, K *out, uint32_t *vout,
+                               int64_t n, hipStream_t s) {
+  constexpr int64_t BS = NT * 16;
+  const int64_t blocks = (n + BS - 1) / BS;
   if (blocks == 0) return hipSuccess;
   auto a16 = [](const void *p) { return ((uintptr_t)p % 16) == 0; };
-  const int vec = a16(in) && a16(out) && (!vout || (a16(vin) && a16(vout)));
-  if (vout)
-    hipLaunchKernelGGL((blocksort_kernel<K, true>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       in, vin, out, vout, n, vec);
-  else
-    hipLaunchKernelGGL((blocksort_kernel<K, false>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       in, vin, out, vout, n, vec);
+  const int vec = a16(in) && a16(out) && (!KV || (a16(vin) && a16(vout)));
+  hipLaunchKernelGGL((blocksort_kernel<K, KV, NT>), dim3((unsigned)blocks), dim3(NT), 0, s, in,
+                     vin, out, vout, n, vec);
   return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_blocksort(const K *in, const uint32_t *vin, K *out, uint32_t *vout,
+                            int64_t n, int log2_block, hipStream_t s) {
+  const bool kv = vout != nullptr;
+  switch (log2_block) {
+    case 12:
+      return kv ? launch_blocksort_nt<K, true, 256>(in, vin, out, vout, n, s)
+                : launch_blocksort_nt<K, false, 256>(in, vin, out, vout, n, s);
+    case 13:
+      return kv ? launch_blocksort_nt<K, true, 512>(in, vin, out, vout, n, s)
+                : launch_blocksort_nt<K, false, 512>(in, vin, out, vout, n, s);
+    case 14:
+      if (kv) {
+        // 16384 keys of 8 bytes with their values exceed a workgroup's LDS
+        if constexpr (sizeof(K) == 8) return hipErrorInvalidValue;
+        else return launch_blocksort_nt<K, true, 1024>(in, vin, out, vout, n, s);
+      }
+      return launch_blocksort_nt<K, false, 1024>(in, vin, out, vout, n, s);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 #define MP_INSTANTIATE(K)                                                        \
   template hipError_t launch_blocksort<K>(const K *, const uint32_t *, K *,      \
-                                          uint32_t *, int64_t, hipStream_t);
+                                          uint32_t *, int64_t, int, hipStream_t);
 MP_INSTANTIATE(uint32_t)
 MP_INSTANTIATE(int32_t)
 MP_INSTANTIATE(uint64_t)

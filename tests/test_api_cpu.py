@@ -91,8 +91,12 @@ def test_sort_and_batched_argument_errors(L):
     assert L.mp_sort(MP_U32, MP_NONE, k, None, 100_000, None, 0, None) == WORKSPACE
     need = L.mp_sort_workspace_bytes(MP_U32, MP_U32, 1000)
     assert need >= 1000 * 8
-    blk = L.mp_sort_block_keys()
-    assert blk >= 2048 and blk & (blk - 1) == 0
+    for kt in (MP_U32, MP_I32, MP_U64, MP_F32):
+        for vt in (MP_NONE, MP_U32, MP_I32, MP_F32):
+            blk = L.mp_sort_block_keys(kt, vt)
+            assert blk >= 4096 and blk & (blk - 1) == 0, (kt, vt)
+    assert L.mp_sort_block_keys(99, MP_NONE) == 0
+    assert L.mp_sort_block_keys(MP_U32, MP_U64) == 0
     assert L.mp_sort(MP_U32, MP_U32, k, None, 1000, ws, need, None) == INVALID
     assert L.mp_sort(MP_U32, MP_NONE, k, P(0x20000), 1000, ws, need, None) == INVALID
     assert L.mp_sort(MP_U32, MP_NONE, k, None, 1000, P(0x10000 + 64), need, None) == OVERLAP

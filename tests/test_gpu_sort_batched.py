@@ -24,7 +24,8 @@ def mp():
 # ------------------------------------------------------------------ sort
 
 @pytest.mark.parametrize("n", [0, 1, 2, 7, 17, 2047, 2048, 2049, 4095, 4096, 4097, 6145, 8191,
-                               8193, 12_289, 100_003, 1 << 20])
+                               8192, 8193, 12_289, 16_383, 16_384, 16_385, 3 * 16_384 + 5,
+                               100_003, 1 << 20])
 def test_sort_sizes(mp, orc, n):
     from gpu_util import dev, host, first_mismatch
     keys = gen.unsorted_uniform(n, 100 + n)
@@ -44,7 +45,7 @@ def test_sort_dtypes(mp, orc, dt):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("n", [1000, 4097, 5003])
+@pytest.mark.parametrize("n", [1000, 4097, 5003, 8192 + 777, 16_384 + 1001])
 def test_sort_largest_keys_in_partial_blocks(mp, orc, dt, n):
     """The last block pads one lane's registers with the largest key; real
     keys equal to it (and +inf for floats) must still come out in input
@@ -74,6 +75,15 @@ def test_sort_kv_stable(mp, orc, dt):
     wk, wv = orc.sort(keys, vals)
     assert first_mismatch(host(gk), wk) is None
     assert first_mismatch(host(gv), wv) is None
+
+
+def test_sort_block_sizes(mp):
+    """Blocks are sized per key width (and never too large for the LDS)."""
+    import torch
+    b4 = mp.sort_block_keys(torch.uint32)
+    assert b4 == mp.sort_block_keys(torch.float32, torch.uint32) == mp.sort_block_keys(torch.int32)
+    b8 = mp.sort_block_keys(torch.uint64, torch.uint32)
+    assert 4096 <= b8 <= 8192 and 4096 <= b4 <= 16384
 
 
 def test_sort_zipf(mp, orc):
