@@ -88,6 +88,19 @@ mp_status mp_partition(mp_dtype kt, const void *A, int64_t na, const void *B,
                        int64_t *a_split, void *stream);
 
 /*
+ * Lanes per diagonal of mp_partition and mp_partition_learned.  With G > 1
+ * lanes a diagonal's search probes G points per round, cutting the interval
+ * G + 1 ways (Theorem 14's search with a wider cut): about log_{G+1} rounds
+ * of dependent loads instead of log_2, for G times the loads.  That pays
+ * when there are too few diagonals to fill the device.
+ *   lanes  0 = chosen per call (the largest power of two G <= 16 with
+ *          G * n_diag <= 2^14, else 1); 1, 2, 4, ..., 64 = that many
+ *          lanes always.  Results never depend on it.  Applies to later calls
+ *          on every thread; MP_ERR_INVALID_ARG for any other value.
+ */
+mp_status mp_partition_lanes(int32_t lanes);
+
+/*
  * mp_merge -- S = merge of A and B (Algorithm 1: equal-length output tiles,
  * each tile's split by Algorithm 2, tiles merged independently).
  *   S   na+nb keys of dtype kt, must not overlap A or B.

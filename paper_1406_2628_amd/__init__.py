@@ -48,6 +48,7 @@ def _declare(L):
         "mp_last_error": ([], ctypes.c_char_p),
         "mp_version": ([], i32),
         "mp_partition": ([i32, p, i64, p, i64, p, i64, p, p], i32),
+        "mp_partition_lanes": ([i32], i32),
         "mp_merge": ([i32, p, i64, p, i64, p, p], i32),
         "mp_merge_kv": ([i32, i32, p, p, i64, p, p, i64, p, p, p], i32),
         "mp_merge_batched_workspace_bytes": ([i32, i64, i64], sz),
@@ -205,6 +206,12 @@ def partition(A: torch.Tensor, B: torch.Tensor, diag: torch.Tensor,
     _check(lib().mp_partition(kt, _ptr(A), A.numel(), _ptr(B), B.numel(), _ptr(diag),
                               diag.numel(), _ptr(out), _stream(A.device)))
     return out
+
+
+def set_partition_lanes(lanes: int = 0):
+    """Lanes that search one diagonal together in ``partition`` and the
+    learned partition: 0 = chosen per call, else a power of two up to 64."""
+    _check(lib().mp_partition_lanes(lanes))
 
 
 def merge(A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

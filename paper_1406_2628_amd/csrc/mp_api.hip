@@ -560,6 +560,13 @@ mp_status mp_autotune_sort(mp_dtype kt, mp_dtype vt, const void *keys_in, const 
   return autotune(kOpSort, reps, s, run, setup, best);
 }
 
+mp_status mp_partition_lanes(int32_t lanes) {
+  if (lanes < 0 || lanes > 64 || (lanes & (lanes - 1)) != 0)
+    return fail(MP_ERR_INVALID_ARG, "mp_partition_lanes: lanes must be 0 or a power of two <= 64");
+  g_partition_lanes = lanes;
+  return MP_OK;
+}
+
 mp_status mp_get_config(const char *op, mp_config *cfg) {
   const int i = op_index(op);
   if (i < 0 || !cfg) return fail(MP_ERR_INVALID_ARG, "mp_get_config: unknown operation or NULL");

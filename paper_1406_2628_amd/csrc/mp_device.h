@@ -42,6 +42,45 @@ __device__ __forceinline__ I split_search(I d, I lo, I hi, GA ga, GB gb) {
   return lo;
 }
 
+// The same search with G lanes per diagonal (G a power of two, 2..64): the
+// group is an aligned block of G lanes of one wavefront holding the same d,
+// lo and hi.  Each round its lanes probe G points that cut [lo, hi) G + 1
+// ways and the group keeps the part where the predicate turns true (it is
+// monotone along the diagonal, Corollary 12), so about log_{G+1} of the
+// interval rounds of dependent loads replace log_2 of it.  Every lane of
+// the group returns the split.
+template <int G, typename I, typename GA, typename GB>
+__device__ __forceinline__ I group_split_search(I d, I lo, I hi, GA ga, GB gb) {
+  static_assert(G >= 2 && G <= 64 && (G & (G - 1)) == 0, "group size");
+  const int lane = threadIdx.x & 63;
+  const int r = lane & (G - 1);
+  const int base = lane & (64 - G);  // first lane of the group
+  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+  while (lo < hi) {
+    const I span = hi - lo;
+    if (span <= G) {
+      // one probe per remaining candidate
+      const I p = lo + r;
+      const bool pred = r < span && (gb(d - 1 - p) < ga(p));
+      const uint64_t m = (__ballot(pred) >> base) & gmask;
+      return m ? lo + (I)(__ffsll((long long)m) - 1) : hi;
+    }
+    const I p = lo + ((I)(r + 1) * span) / (G + 1);
+    const bool pred = gb(d - 1 - p) < ga(p);
+    const uint64_t m = (__ballot(pred) >> base) & gmask;
+    if (m == 0) {
+      lo = lo + ((I)G * span) / (G + 1) + 1;
+    } else {
+      // first true probe f: the split lies after probe f - 1, at or before f
+      const int f = __ffsll((long long)m) - 1;
+      const I pf = lo + ((I)(f + 1) * span) / (G + 1);
+      lo = f == 0 ? lo : lo + ((I)f * span) / (G + 1) + 1;
+      hi = pf;
+    }
+  }
+  return lo;
+}
+
 // Serial merge of VT outputs from a split, entirely in LDS (Lemma 1; the
 // loser of each compare stays in a register so each step reads one key).
 //   keys: LDS array; A keys at positions [ai, a_end), B keys at [bi, b_end).

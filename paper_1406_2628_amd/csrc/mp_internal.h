@@ -39,6 +39,12 @@ struct TileCfg {
   int vt;
 };
 
+// Lanes that search one diagonal together: g_partition_lanes when set (a
+// power of two, 1..64), else chosen from the number of diagonals so that
+// small launches still fill the device.
+extern int g_partition_lanes;
+int partition_lanes(int64_t n_diag);
+
 // Grid-level split search on explicit diagonals (diag != nullptr) or on the
 // equispaced diagonals k * tile clamped to na + nb (diag == nullptr).
 template <typename K>

@@ -38,6 +38,7 @@
 #include <stdio.h>
 #include <string.h>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mp_device.h"
@@ -87,8 +88,13 @@ __device__ __forceinline__ int64_t lp_prior(int64_t d, int64_t na, int64_t nb) {
 }
 
 // y = w2 . relu(W1 x + b1) + b2 with parameters in p (any address space).
-template <typename PP>
-__device__ __forceinline__ float lp_forward(const PP &p, const float *x, int F, int H) {
+// FC, HC > 0 fix the shape at compile time (F = FC, H = HC; the loops then
+// unroll and constant-offset reads of a kernel-argument pointer become
+// scalar loads); the operations and their order are the same either way, so
+// both give the same bits.
+template <int FC = 0, int HC = 0, typename PP>
+__device__ __forceinline__ float lp_forward(const PP &p, const float *x, int F_, int H_) {
+  const int F = FC > 0 ? FC : F_, H = HC > 0 ? HC : H_;
   const int ob1 = H * F, ow2 = ob1 + H, ob2 = ow2 + H;
   float y = p[ob2];
   for (int j = 0; j < H; ++j) {
@@ -102,12 +108,12 @@ __device__ __forceinline__ float lp_forward(const PP &p, const float *x, int F, 
 // Prediction for diagonal d clipped to the diagonal [dlo, dhi]: the point
 // both calibration and search put their windows around.  A prediction that
 // is not finite (or absurdly large) adds nothing to the prior.
-template <typename PP>
+template <int FC = 0, int HC = 0, typename PP>
 __device__ __forceinline__ int64_t lp_predict(const PP &p, int64_t d, int64_t na, int64_t nb,
                                               int F, int H, int64_t dlo, int64_t dhi) {
   float x[kLpMaxFeatures];
-  lp_features(d, na, nb, F, x);
-  const float ys = lp_forward(p, x, F, H) * (float)na;
+  lp_features(d, na, nb, FC > 0 ? FC : F, x);
+  const float ys = lp_forward<FC, HC>(p, x, F, H) * (float)na;
   const int64_t a = lp_prior(d, na, nb) +
                     (isfinite(ys) && fabsf(ys) < 4.0e18f ? (int64_t)llrintf(ys) : 0);
   return a < dlo ? dlo : (a > dhi ? dhi : a);
@@ -290,18 +296,26 @@ __global__ void lp_error_kernel(const float *__restrict__ params, const int64_t 
 // ---- inference: predicted window + exact search + certificate ------------
 
 // windows: kLpBuckets (lo, hi) offset pairs (device), or NULL for the
-// symmetric window [-window, window] on every diagonal.
-template <typename K>
+// symmetric window [-window, window] on every diagonal.  G lanes per
+// diagonal (G = 1: split_search; G > 1: group_split_search, every lane of
+// the group evaluating the same model and lane 0 writing).  FC, HC > 0: a
+// model of that shape compiled in, its weights read straight from
+// `params` (scalar loads, no LDS staging or barrier); 0: any shape, weights
+// staged in LDS.
+template <typename K, int G, int FC, int HC>
 __global__ __launch_bounds__(256) void learned_partition_kernel(
     const float *__restrict__ params, int F, int H, int64_t window,
     const int64_t *__restrict__ windows, const K *__restrict__ A, int64_t na,
     const K *__restrict__ B, int64_t nb, const int64_t *__restrict__ diag, int64_t n_diag,
     int64_t *__restrict__ a_split, unsigned long long *__restrict__ n_fallback) {
-  __shared__ float sp[kLpMaxParams];
-  const int P = lp_num_params(F, H);
-  for (int i = threadIdx.x; i < P; i += blockDim.x) sp[i] = params[i];
-  __syncthreads();
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float sp[FC > 0 ? 1 : kLpMaxParams];
+  if constexpr (FC == 0) {
+    const int P = lp_num_params(F, H);
+    for (int i = threadIdx.x; i < P; i += blockDim.x) sp[i] = params[i];
+    __syncthreads();
+  }
+  // groups never straddle a workgroup (G divides 256), so a group exits as one
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   if (k >= n_diag) return;
   const int64_t n = na + nb;
   int64_t d = diag[k];
@@ -315,24 +329,31 @@ __global__ __launch_bounds__(256) void learned_partition_kernel(
     wlo = windows[2 * b];
     whi = windows[2 * b + 1];
   }
-  const int64_t ahat = lp_predict(sp, d, na, nb, F, H, dlo, dhi);
+  int64_t ahat;
+  if constexpr (FC > 0) ahat = lp_predict<FC, HC>(params, d, na, nb, F, H, dlo, dhi);
+  else ahat = lp_predict(sp, d, na, nb, F, H, dlo, dhi);
   // wlo <= whi, so lo <= hi
   const int64_t lo = lp_edge(ahat, wlo, dlo, dhi);
   const int64_t hi = lp_edge(ahat, whi, dlo, dhi);
   auto ga = [&](int64_t i) { return A[i]; };
   auto gb = [&](int64_t j) { return B[j]; };
-  int64_t a = split_search<int64_t>(d, lo, hi, ga, gb);
+  auto search = [&](int64_t l, int64_t h) -> int64_t {
+    if constexpr (G == 1) return split_search<int64_t>(d, l, h, ga, gb);
+    else return group_split_search<G, int64_t>(d, l, h, ga, gb);
+  };
+  int64_t a = search(lo, hi);
   // Certificate, needed only on a window edge that is not a diagonal bound:
   // at a == hi the predicate B[d-1-a] < A[a] was never probed; at a == lo
   // its failure at a - 1 was never probed.
   bool ok = true;
   if (a == hi && hi < dhi) ok = B[d - 1 - a] < A[a];
   if (ok && a == lo && lo > dlo) ok = !(B[d - a] < A[a - 1]);
+  const bool first = (threadIdx.x & (G - 1)) == 0;
   if (!ok) {
-    a = split_search<int64_t>(d, dlo, dhi, ga, gb);
-    if (n_fallback) atomicAdd(n_fallback, 1ull);
+    a = search(dlo, dhi);
+    if (n_fallback && first) atomicAdd(n_fallback, 1ull);
   }
-  a_split[k] = a;
+  if (first) a_split[k] = a;
 }
 
 // ---- host side ----------------------------------------------------------------
@@ -744,13 +765,31 @@ mp_status mp_partition_learned(mp_lp h, mp_dtype kt, const void *A, int64_t na, 
   if (n_diag == 0) return MP_OK;
   hipStream_t s = (hipStream_t)stream;
   KernelTimer timer("partition_learned", s);
+  const int g = partition_lanes(n_diag);
+  const unsigned blocks = (unsigned)((n_diag * g + 255) / 256);
   dispatch_key(kt, [&](auto k) {
     using KT = decltype(k);
-    hipLaunchKernelGGL((learned_partition_kernel<KT>), dim3((unsigned)((n_diag + 255) / 256)),
-                       dim3(256), 0, s, (const float *)h->params, h->F, h->H, h->window,
-                       h->windows.empty() ? nullptr : (const int64_t *)h->d_windows,
-                       (const KT *)A, na, (const KT *)B, nb, diag, n_diag, a_split,
-                       (unsigned long long *)n_fallback);
+    const int64_t *wt = h->windows.empty() ? nullptr : (const int64_t *)h->d_windows;
+    auto go = [&](auto kernel) {
+      hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, (const float *)h->params, h->F,
+                         h->H, h->window, wt, (const KT *)A, na, (const KT *)B, nb, diag, n_diag,
+                         a_split, (unsigned long long *)n_fallback);
+    };
+    // the default model shape (5 inputs, 32 hidden units) is compiled in
+    auto by_shape = [&](auto gc) {
+      constexpr int G = decltype(gc)::value;
+      if (h->F == 5 && h->H == 32) go(learned_partition_kernel<KT, G, 5, 32>);
+      else go(learned_partition_kernel<KT, G, 0, 0>);
+    };
+    switch (g) {
+      case 2: by_shape(std::integral_constant<int, 2>()); break;
+      case 4: by_shape(std::integral_constant<int, 4>()); break;
+      case 8: by_shape(std::integral_constant<int, 8>()); break;
+      case 16: by_shape(std::integral_constant<int, 16>()); break;
+      case 32: by_shape(std::integral_constant<int, 32>()); break;
+      case 64: by_shape(std::integral_constant<int, 64>()); break;
+      default: by_shape(std::integral_constant<int, 1>());
+    }
   });
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MP_OK : lp_hip(e, "mp_partition_learned launch");

@@ -123,6 +123,13 @@ def test_config_errors(L):
     mp.set_config("merge", None)
 
 
+def test_partition_lanes_argument_errors(L):
+    for bad in (-1, 3, 65, 128):
+        assert L.mp_partition_lanes(bad) == INVALID
+    for ok in (1, 2, 4, 8, 16, 32, 64, 0):
+        assert L.mp_partition_lanes(ok) == OK
+
+
 def test_partition_argument_errors(L):
     a, b, d, o = P(0x10000), P(0x20000), P(0x30000), P(0x40000)
     assert L.mp_partition(0, a, 4, b, 4, d, 4, o, None) == UNSUPPORTED

@@ -217,6 +217,32 @@ def test_unbounded_window_is_the_full_search(mp, orc, trained, tmp_path):
     _check_identical(mp, orc, big, A, B, diag, expect_fallback=False)
 
 
+@pytest.mark.parametrize("lanes", [1, 4, 16, 64])
+def test_learned_lanes_per_diagonal(mp, orc, trained, lanes):
+    """The group searches of the learned partition (window, certificate and
+    fallback) give the plain search's splits for every group size."""
+    import torch
+    from gpu_util import dev, host
+    lp, _, _, _, n = trained
+    A, B = gen.f32_mixture_pair(n, n, 60)
+    diag = np.concatenate([[0, 1, n, 2 * n - 1, 2 * n],
+                           np.random.default_rng(lanes).integers(0, 2 * n + 1, 3001)]).astype(np.int64)
+    mp.set_partition_lanes(lanes)
+    try:
+        _check_identical(mp, orc, lp, A, B, diag)
+        # a zero window sends every diagonal off its window edge to the fallback
+        narrow = mp.LearnedPartitioner(H, F, 3)
+        narrow.set_params(lp.get_params())
+        narrow.window = 0
+        _check_identical(mp, orc, narrow, A, B, diag, expect_fallback=True)
+        # a model of another shape runs the kernel whose shape is not compiled in
+        other = mp.LearnedPartitioner(7, 3, 4)
+        other.window = 1000
+        _check_identical(mp, orc, other, A, B, diag)
+    finally:
+        mp.set_partition_lanes(0)
+
+
 def test_garbage_model_still_exact(mp, orc):
     lp = mp.LearnedPartitioner(H, F, 1)
     p = np.full(lp.num_params, 1e30, np.float32)

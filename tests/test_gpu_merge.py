@@ -94,6 +94,31 @@ def test_partition(mp, orc, dt):
     assert np.array_equal(got, orc.partition(A, B, diag))
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64, 0])
+def test_partition_lanes_per_diagonal(mp, orc, lanes):
+    """Every group size of the search (forced, and chosen per call for launch
+    sizes that pick different groups) gives the oracle's splits."""
+    from gpu_util import dev, host
+    mp.set_partition_lanes(lanes)
+    try:
+        for dt in (gen.U32, gen.I32, gen.U64, gen.F32):
+            A, B = gen.uniform_pair(70_001, 40_003, 5, dt)
+            n = len(A) + len(B)
+            for n_diag in (1, 3, 65, 5003, 20_011, 70_001):
+                g = np.random.default_rng(n_diag)
+                diag = np.concatenate([[0, n, 1, n - 1], g.integers(-5, n + 6, n_diag)]).astype(np.int64)
+                got = host(mp.partition(dev(A), dev(B), dev(diag)))
+                assert np.array_equal(got, orc.partition(A, B, np.clip(diag, 0, n))), (dt, n_diag)
+        for (na, nb) in [(1, 100_000), (100_000, 1), (0, 10), (10, 0), (30_000, 30_000)]:
+            A, B = gen.dups_pair(na, nb, 9, hi=7)
+            n = na + nb
+            diag = np.arange(0, n + 1, max(1, n // 997), dtype=np.int64)
+            got = host(mp.partition(dev(A), dev(B), dev(diag)))
+            assert np.array_equal(got, orc.partition(A, B, diag)), (na, nb)
+    finally:
+        mp.set_partition_lanes(0)
+
+
 def test_partition_dups_and_skew(mp, orc):
     from gpu_util import dev, host
     for (na, nb) in [(1, 100_000), (100_000, 1), (0, 10), (10, 0)]:
