@@ -108,6 +108,7 @@ def profiled_traffic():
 
 # ---------------------------------------------------------------------------
 def leg_headline(args, out):
+    import numpy as np
     import torch
 
     import mp_inputs as gen
@@ -170,6 +171,14 @@ def leg_headline(args, out):
                      "kernel_ms": round(kern_ms, 4),
                      "window_reload_rate": round(reloads / max(1, tiles), 6)},
     })
+    # The same merge kept in registers (nothing stored; section 6's runs
+    # that write to a local register): reading and comparing alone.
+    log("bench: headline: timing the no-store merge (mp_merge_checksum)")
+    ck = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    nw_ms = time_steps(lambda: mp.merge_checksum(dA, dB, out=ck), args.steps, args.warmup)
+    ck.zero_()
+    mp.merge_checksum(dA, dB, out=ck)
+    ck_got = int(ck.cpu().numpy()[0])
     S = dS.cpu().numpy()
     del dA, dB, dS
     if args.no_cpu_baseline:
@@ -193,6 +202,14 @@ def leg_headline(args, out):
             "sample": f"the full headline workload, median of {len(times)} single-threaded runs "
                       f"(1 of {os.cpu_count()} host threads)"}
     out["bit_exact"] = bool(S.tobytes() == ref.tobytes())
+    with np.errstate(over="ignore"):
+        ck_want = int(np.sum(ref.astype(np.uint64) * np.arange(1, n_out + 1, dtype=np.uint64),
+                             dtype=np.uint64))
+    out["no_write"] = {"ms": round(nw_ms, 4), "Gkeys_s": round(n_out / (nw_ms * 1e-3) / 1e9, 2),
+                       "read_GBs": round(n_out * 4 / (nw_ms * 1e-3) / 1e9, 1),
+                       "read_frac": round(n_out * 4 / (nw_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "store_over_no_store": round(ms / nw_ms, 3),
+                       "checksum_matches_oracle": ck_got == ck_want}
 
 
 # ---------------------------------------------------------------------------

@@ -109,6 +109,23 @@ mp_status mp_merge(mp_dtype kt, const void *A, int64_t na, const void *B,
                    int64_t nb, void *S, void *stream);
 
 /*
+ * mp_merge_checksum -- the merge of A and B computed but not written: the
+ * runs of section 6 whose merged values go to a local register instead of
+ * memory, which isolate reading and comparing from storing.  Every output
+ * stays in the registers of the lane that merged it; the kernel adds
+ *     sum over i of S[i] * (i + 1)   (modulo 2^64; keys as unsigned bits,
+ *                                     4-byte keys zero-extended)
+ * to *checksum, where S is the merge mp_merge would write, so the result
+ * still depends on every output and its position.
+ *   checksum  one uint64 in device memory (8-byte aligned), added to, not
+ *             overwritten: zero it first.
+ * A diagnostic for measurement; it uses the persistent kernel with the
+ * merge's current tile if that is 192 x 24 or 256 x 16, else 192 x 24.
+ */
+mp_status mp_merge_checksum(mp_dtype kt, const void *A, int64_t na, const void *B,
+                            int64_t nb, uint64_t *checksum, void *stream);
+
+/*
  * mp_merge_kv -- key-value merge: keys as mp_merge; each value travels with
  * its key (stable: equal keys keep A's values before B's, each input's own
  * order preserved).

@@ -50,6 +50,7 @@ def _declare(L):
         "mp_partition": ([i32, p, i64, p, i64, p, i64, p, p], i32),
         "mp_partition_lanes": ([i32], i32),
         "mp_merge": ([i32, p, i64, p, i64, p, p], i32),
+        "mp_merge_checksum": ([i32, p, i64, p, i64, p, p], i32),
         "mp_merge_kv": ([i32, i32, p, p, i64, p, p, i64, p, p, p], i32),
         "mp_merge_batched_workspace_bytes": ([i32, i64, i64], sz),
         "mp_merge_batched": ([i32, p, p, p, p, i64, i64, i64, p, p, sz, p], i32),
@@ -205,6 +206,17 @@ def partition(A: torch.Tensor, B: torch.Tensor, diag: torch.Tensor,
         out = torch.empty(diag.numel(), dtype=torch.int64, device=A.device)
     _check(lib().mp_partition(kt, _ptr(A), A.numel(), _ptr(B), B.numel(), _ptr(diag),
                               diag.numel(), _ptr(out), _stream(A.device)))
+    return out
+
+
+def merge_checksum(A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Merge without writing it: adds sum(S[i] * (i + 1)) mod 2^64 (keys as
+    unsigned bits) to ``out`` (a zeroed uint64 device scalar when None)."""
+    kt = _key_dtype(A, B)
+    if out is None:
+        out = torch.zeros(1, dtype=torch.uint64, device=A.device)
+    _check(lib().mp_merge_checksum(kt, _ptr(A), A.numel(), _ptr(B), B.numel(), _ptr(out),
+                                   _stream(A.device)))
     return out
 
 

@@ -247,6 +247,39 @@ mp_status mp_merge(mp_dtype kt, const void *A, int64_t na, const void *B,
                       nullptr, stream);
 }
 
+mp_status mp_merge_checksum(mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb,
+                            uint64_t *checksum, void *stream) {
+  const char *fn = "mp_merge_checksum";
+  if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported key dtype %d", fn, (int)kt);
+  const size_t es = dtype_size(kt);
+  mp_status st;
+  if ((st = check_array(A, na, es, "A")) != MP_OK) return st;
+  if ((st = check_array(B, nb, es, "B")) != MP_OK) return st;
+  if (na > INT64_MAX - nb) return fail(MP_ERR_INVALID_ARG, "%s: na + nb overflows", fn);
+  if (!checksum || (uintptr_t)checksum % 8)
+    return fail(MP_ERR_INVALID_ARG, "%s: checksum must be an 8-byte aligned device pointer", fn);
+  const Range rc = span(checksum, 1, 8);
+  if (overlaps(rc, span(A, na, es)) || overlaps(rc, span(B, nb, es)))
+    return fail(MP_ERR_OVERLAP, "%s: checksum overlaps an input", fn);
+  if (na + nb == 0) return MP_OK;
+  mp_config cfg = current_config(kOpMerge);
+  // the persistent kernel with the merge's tile when it has a no-store
+  // variant, else the built-in tile
+  if (cfg.mode != 2 || !((cfg.nt == 192 && cfg.vt == 24) || (cfg.nt == 256 && cfg.vt == 16))) {
+    cfg = kDefaultConfig[kOpMerge];
+  }
+  const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  dispatch_key(kt, [&](auto k) {
+    using K = decltype(k);
+    KernelTimer timer("merge_checksum", s);
+    e = launch_merge_checksum<K>(sc, (const K *)A, na, (const K *)B, nb,
+                                 (unsigned long long *)checksum, s);
+  });
+  return e == hipSuccess ? MP_OK : hip_fail(e, "mp_merge_checksum launch");
+}
+
 mp_status mp_merge_kv(mp_dtype kt, mp_dtype vt, const void *Ak, const void *Av,
                       int64_t na, const void *Bk, const void *Bv, int64_t nb,
                       void *Sk, void *Sv, void *stream) {

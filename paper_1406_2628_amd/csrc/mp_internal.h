@@ -77,6 +77,12 @@ hipError_t launch_merge_stream(StreamCfg cfg, const K *A, const uint32_t *Av,
                                int64_t na, const K *B, const uint32_t *Bv,
                                int64_t nb, K *S, uint32_t *Sv, hipStream_t s);
 
+// Persistent merge that stores nothing: adds sum of S[i] * (i + 1) (keys as
+// unsigned bits, modulo 2^64) to *checksum.  Tiles 192 x 24 or 256 x 16.
+template <typename K>
+hipError_t launch_merge_checksum(StreamCfg cfg, const K *A, int64_t na, const K *B, int64_t nb,
+                                 unsigned long long *checksum, hipStream_t s);
+
 // Batched merge of CSR-concatenated pairs (persistent, one launch).
 template <typename K>
 hipError_t launch_merge_batched(StreamCfg cfg, const K *A, const int64_t *a_off,

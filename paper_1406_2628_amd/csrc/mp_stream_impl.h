@@ -45,6 +45,8 @@
 // remains for a workgroup's first tile and as an option.
 #pragma once
 
+#include <type_traits>
+
 #include "mp_device.h"
 #include "mp_internal.h"
 
@@ -65,6 +67,7 @@ struct PairArgs {
   const int64_t *a_off, *b_off;  // kExplicit
   int64_t n_pairs;
   unsigned long long *stats;     // optional: [tiles, window reloads]
+  unsigned long long *checksum;  // no-store launches: sum of S[i] * (i + 1) added here
 };
 
 // Split on diagonal d of the grid A'[lo_a ...] x B' restricted to candidate
@@ -175,7 +178,11 @@ __device__ __forceinline__ Window make_window(int64_t a_cur, int64_t b_cur,
   return w;
 }
 
-template <typename K, bool KV, int NT, int VT, int KIND, bool VECTOR>
+// STORE = false: the diagnostic run that keeps the merged outputs in
+// registers (the paper's runs that write to a local register): no output
+// stage and no stores; each lane adds S[i] * (i + 1) over its outputs (keys
+// as unsigned bits, modulo 2^64), one atomic per wavefront at the end.
+template <typename K, bool KV, int NT, int VT, int KIND, bool VECTOR, bool STORE = true>
 __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   constexpr int T = NT * VT;
   constexpr int VEC = 16 / (int)sizeof(K);
@@ -584,6 +591,7 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   };
 
   unsigned long long n_reload = 0;
+  unsigned long long ck = 0;  // STORE = false: this lane's checksum
   for (int64_t t = t_begin; t < t_end; ++t) {
     d0 = t * T;
     const int n = w.n;
@@ -695,6 +703,14 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     }
     __syncthreads();
 
+    if constexpr (!STORE) {
+      typedef typename std::conditional<sizeof(K) == 8, uint64_t, uint32_t>::type Bits;
+#pragma unroll
+      for (int i = 0; i < VT; ++i)
+        if (i < steps)
+          ck += (unsigned long long)__builtin_bit_cast(Bits, out[i]) *
+                (unsigned long long)(d0 + dl + i + 1);
+    } else {
     bool staged = false;
     // full tile: each lane's VT outputs with the widest LDS store that
     // divides its run (16 or 8 bytes)
@@ -763,6 +779,7 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
       }
     }
     __syncthreads();
+    }  // STORE
 
     if (more) {
       if (speculate) commit(wn);
@@ -782,13 +799,18 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
     kl = kl_next;
     w = wn;
   }
+  if constexpr (!STORE) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ck += __shfl_xor(ck, o);
+    if ((tid & 63) == 0) atomicAdd(P.checksum, ck);
+  }
   if (P.stats && tid == 0) {
     atomicAdd(&P.stats[0], (unsigned long long)(t_end - t_begin));
     atomicAdd(&P.stats[1], n_reload);
   }
 }
 
-template <typename K, bool KV, int NT, int VT, int KIND>
+template <typename K, bool KV, int NT, int VT, int KIND, bool STORE = true>
 static hipError_t launch_pairs_impl(int grid, bool vec, PairArgs<K> args, hipStream_t s) {
   constexpr int64_t T = NT * VT;
   args.n_tiles = (args.NA + args.NB + T - 1) / T;
@@ -800,7 +822,7 @@ static hipError_t launch_pairs_impl(int grid, bool vec, PairArgs<K> args, hipStr
     if (per_cu == 0) {
       int occ = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-              &occ, merge_pairs_kernel<K, KV, NT, VT, KIND, true>, NT, 0) != hipSuccess ||
+              &occ, merge_pairs_kernel<K, KV, NT, VT, KIND, true, STORE>, NT, 0) != hipSuccess ||
           occ <= 0)
         occ = 1;
       per_cu = occ;
@@ -810,10 +832,10 @@ static hipError_t launch_pairs_impl(int grid, bool vec, PairArgs<K> args, hipStr
   g_last_pairs_grid = grid;
   const int64_t G = grid < args.n_tiles ? grid : args.n_tiles;
   if (vec)
-    hipLaunchKernelGGL((merge_pairs_kernel<K, KV, NT, VT, KIND, true>), dim3((unsigned)G),
+    hipLaunchKernelGGL((merge_pairs_kernel<K, KV, NT, VT, KIND, true, STORE>), dim3((unsigned)G),
                        dim3(NT), 0, s, args);
   else
-    hipLaunchKernelGGL((merge_pairs_kernel<K, KV, NT, VT, KIND, false>), dim3((unsigned)G),
+    hipLaunchKernelGGL((merge_pairs_kernel<K, KV, NT, VT, KIND, false, STORE>), dim3((unsigned)G),
                        dim3(NT), 0, s, args);
   return hipGetLastError();
 }
@@ -851,6 +873,23 @@ hipError_t launch_merge_stream(StreamCfg cfg, const K *A, const uint32_t *Av,
   const bool vec = aligned16(A) && aligned16(B) && aligned16(S) &&
                    (!kv || (aligned16(Sv) && aligned16(Av) && aligned16(Bv)));
   return launch_pairs<K, kSingle>(cfg, vec, a, s);
+}
+
+// No-store merge (see merge_pairs_kernel): keys only, the merge's built-in
+// 192 x 24 tiles or 256 x 16.
+template <typename K>
+hipError_t launch_merge_checksum(StreamCfg cfg, const K *A, int64_t na, const K *B, int64_t nb,
+                                 unsigned long long *checksum, hipStream_t s) {
+  PairArgs<K> a{};
+  a.A = A; a.B = B;
+  a.NA = na; a.NB = nb; a.margin = cfg.margin;
+  a.checksum = checksum;
+  const bool vec = aligned16(A) && aligned16(B);
+  if (cfg.nt == 256 && cfg.vt == 16)
+    return launch_pairs_impl<K, false, 256, 16, kSingle, false>(cfg.grid, vec, a, s);
+  if (cfg.nt == 192 && cfg.vt == 24)
+    return launch_pairs_impl<K, false, 192, 24, kSingle, false>(cfg.grid, vec, a, s);
+  return hipErrorNotSupported;
 }
 
 template <typename K>
@@ -893,6 +932,8 @@ hipError_t launch_sort_round(StreamCfg cfg, const K *X, const uint32_t *Xv, K *Y
   template hipError_t launch_merge_stream<K>(StreamCfg, const K *, const uint32_t *,     \
                                              int64_t, const K *, const uint32_t *,       \
                                              int64_t, K *, uint32_t *, hipStream_t);     \
+  template hipError_t launch_merge_checksum<K>(StreamCfg, const K *, int64_t, const K *, \
+                                               int64_t, unsigned long long *, hipStream_t); \
   template hipError_t launch_merge_batched<K>(StreamCfg, const K *, const int64_t *,     \
                                               const K *, const int64_t *, int64_t,       \
                                               int64_t, int64_t, K *, hipStream_t);       \

@@ -65,6 +65,16 @@ def test_merge_argument_errors(L):
     assert L.mp_merge(MP_U64, a, 1 << 62, b, 1 << 62, s, None) in (INVALID, OVERLAP)
 
 
+def test_merge_checksum_argument_errors(L):
+    a, b, c = P(0x10000), P(0x20000), P(0x30000)
+    assert L.mp_merge_checksum(99, a, 10, b, 10, c, None) == UNSUPPORTED
+    assert L.mp_merge_checksum(MP_U32, a, 10, b, 10, None, None) == INVALID
+    assert L.mp_merge_checksum(MP_U32, a, 10, b, 10, P(0x30004), None) == INVALID   # misaligned
+    assert L.mp_merge_checksum(MP_U32, a, 16, b, 16, P(0x10000 + 8), None) == OVERLAP
+    assert L.mp_merge_checksum(MP_U32, a, -1, b, 10, c, None) == INVALID
+    assert L.mp_merge_checksum(MP_U32, None, 0, None, 0, c, None) == OK          # empty no-op
+
+
 def test_merge_kv_argument_errors(L):
     ak, av, bk, bv, sk, sv = (P(x) for x in (0x10000, 0x20000, 0x30000, 0x40000, 0x50000, 0x60000))
     assert L.mp_merge_kv(MP_U32, MP_NONE, ak, av, 4, bk, bv, 4, sk, sv, None) == INVALID

@@ -94,6 +94,33 @@ def test_partition(mp, orc, dt):
     assert np.array_equal(got, orc.partition(A, B, diag))
 
 
+def _position_checksum(S):
+    """sum of S[i] * (i + 1) modulo 2^64, keys as unsigned bits."""
+    bits = S.view(np.uint64) if S.dtype.itemsize == 8 else S.view(np.uint32).astype(np.uint64)
+    with np.errstate(over="ignore"):
+        return int(np.sum(bits * np.arange(1, len(S) + 1, dtype=np.uint64), dtype=np.uint64))
+
+
+@pytest.mark.parametrize("cfg", [None, (2, 256, 16, 0, 0), (2, 192, 24, 5, 0), (2, 256, 16, 0, 64)])
+def test_merge_checksum_no_store(mp, orc, cfg):
+    """The merge kept in registers (nothing stored) accounts for every output
+    at its position: its checksum equals the oracle merge's."""
+    from gpu_util import dev, host
+    if cfg is not None:
+        mp.set_config("merge", *cfg)
+    try:
+        cases = [gen.uniform_pair(300_007, 200_003, 61, dt) for dt in DTYPES]
+        cases += [gen.dups_pair(150_001, 90_007, 62, hi=50), gen.disjoint_pair(70_000, 50_001, 63),
+                  gen.uniform_pair(0, 5000, 64), gen.uniform_pair(4999, 0, 65), gen.uniform_pair(1, 1, 66)]
+        A, B = gen.f32_mixture_pair(100_000, 80_001, 67)
+        cases.append((A, B))
+        for A, B in cases:
+            got = int(host(mp.merge_checksum(dev(A), dev(B)))[0])
+            assert got == _position_checksum(orc.merge(A, B)), (A.dtype, len(A), len(B))
+    finally:
+        mp.set_config("merge", None)
+
+
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64, 0])
 def test_partition_lanes_per_diagonal(mp, orc, lanes):
     """Every group size of the search (forced, and chosen per call for launch
