@@ -301,7 +301,11 @@ mp_status mp_lp_load(mp_lp *h, const char *path);
  *                    input;
  *               <0 = full windows (n keys of each input per tile of n
  *                    outputs).
- * Returns MP_ERR_UNSUPPORTED for an (nt, vt) pair that is not compiled in.
+ * Persistent (nt, vt) pairs compiled in: (192, 24), (256, 8), (256, 12),
+ * (256, 14), (256, 16), (256, 18), (128, 16), (512, 8), and (512, 16) for
+ * 4-byte keys; per-tile mode: (256, 8), (256, 15), (256, 16), (128, 16).
+ * A call with a pair that is not compiled in for its key type returns
+ * MP_ERR_UNSUPPORTED.
  */
 typedef struct {
   int32_t mode;

@@ -466,8 +466,8 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
 // returns it.  `setup`, when given, runs untimed before every call (the sort
 // restores its unsorted input).
 
-static const int kTuneShapes[][2] = {{192, 24}, {256, 16}, {256, 18}, {256, 14},
-                                     {256, 12}, {256, 8},  {128, 16}, {512, 8}};
+static const int kTuneShapes[][2] = {{192, 24}, {256, 16}, {256, 18}, {256, 14}, {256, 12},
+                                     {256, 8},  {128, 16}, {512, 8},   {512, 16}};
 
 template <typename Run, typename Setup>
 static mp_status autotune(Op op, int reps, hipStream_t s, Run run, Setup setup, mp_config *best) {

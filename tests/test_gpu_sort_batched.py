@@ -108,7 +108,8 @@ def test_sort_rejects_tiles_that_do_not_divide_run_pairs(mp):
 
 
 @pytest.mark.parametrize("variant", [(2, 256, 8, 0, 0), (2, 512, 8, 0, 0), (2, 128, 16, 0, 0),
-                                     (2, 256, 16, 0, -1), (2, 256, 16, 0, 1), (2, 128, 16, 3, 0)])
+                                     (2, 512, 16, 0, 0), (2, 256, 16, 0, -1), (2, 256, 16, 0, 1),
+                                     (2, 128, 16, 3, 0)])
 def test_sort_round_variants(mp, orc, variant):
     from gpu_util import dev, host, first_mismatch
     mp.set_config("sort", *variant)
@@ -171,7 +172,8 @@ def test_batched_dtypes_dups(mp, orc, dt):
 
 
 @pytest.mark.parametrize("variant", [(2, 256, 8, 0, 0), (2, 256, 12, 0, 0), (2, 512, 8, 0, 0),
-                                     (2, 256, 16, 0, -1), (2, 256, 16, 0, 1), (2, 128, 16, 5, 0)])
+                                     (2, 512, 16, 0, 0), (2, 256, 16, 0, -1), (2, 256, 16, 0, 1),
+                                     (2, 128, 16, 5, 0)])
 def test_batched_variants(mp, orc, variant):
     from gpu_util import dev, host, first_mismatch
     mp.set_config("batched", *variant)
