@@ -1,0 +1,103 @@
+"""Parity at sizes past 2^31 and 2^32 elements (64-bit index paths), checked
+on the device against closed forms that hold at any size.
+
+* Merge: A[i] = floor(i / 2) and B[j] = floor(j / 2), |A| = |B| = 3 * 2^30.
+  Every value appears twice in each input, and ties take A first, so the
+  merge holds each value four times: S[p] = floor(p / 4) over 3 * 2^31
+  outputs, and the split on diagonal d = 4v + r is a = 2v + min(r, 2).
+* Sort: keys k_i = (i * 0x9E3779B1) mod 2^32 for i < 2^31 + 12345 are
+  distinct (multiplying by an odd constant is a bijection modulo 2^32), so
+  with values v_i = i the sorted keys must increase strictly and every value
+  must still map to its key.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+CHUNK = 1 << 28
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1406_2628_amd as mp
+    mp.lib()
+    return mp
+
+
+def _need(gib):
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    if free < gib * (1 << 30):
+        pytest.skip(f"needs {gib} GiB of free device memory")
+
+
+def _u32_from(x64):
+    """int64 tensor with values in [0, 2^32) -> uint32 tensor (same values)."""
+    import torch
+    return x64.to(torch.int32).view(torch.uint32)
+
+
+def _half_index(n):
+    """uint32 tensor t[i] = floor(i / 2), built in chunks."""
+    import torch
+    t = torch.empty(n, dtype=torch.uint32, device="cuda")
+    for s in range(0, n, CHUNK):
+        e = min(n, s + CHUNK)
+        t[s:e] = _u32_from(torch.arange(s, e, dtype=torch.int64, device="cuda") >> 1)
+    return t
+
+
+def test_merge_and_partition_past_2p32_outputs(mp):
+    import torch
+    _need(56)
+    na = nb = 3 << 30
+    A = _half_index(na)
+    B = _half_index(nb)
+    S = torch.empty(na + nb, dtype=torch.uint32, device="cuda")
+    mp.merge(A, B, out=S)
+    torch.cuda.synchronize()
+    N = na + nb
+    assert N > 1 << 32
+    for s in range(0, N, CHUNK):
+        e = min(N, s + CHUNK)
+        want = torch.arange(s, e, dtype=torch.int64, device="cuda") >> 2
+        got = S[s:e].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        assert torch.equal(got, want), s
+    del S
+    g = np.random.default_rng(5)
+    d = np.concatenate([[0, 1, 2, 3, N - 1, N, (1 << 31) - 1, 1 << 31, (1 << 32) - 1, 1 << 32,
+                         (1 << 32) + 1], g.integers(0, N + 1, 20000)]).astype(np.int64)
+    got = mp.partition(A, B, torch.from_numpy(d).cuda()).cpu().numpy()
+    want = 2 * (d // 4) + np.minimum(d % 4, 2)
+    assert np.array_equal(got, want)
+
+
+def test_sort_kv_past_2p31_keys(mp):
+    import torch
+    _need(40)
+    n = (1 << 31) + 12345
+    c = 0x9E3779B1
+    keys = torch.empty(n, dtype=torch.uint32, device="cuda")
+    vals = torch.empty(n, dtype=torch.uint32, device="cuda")
+    for s in range(0, n, CHUNK):
+        e = min(n, s + CHUNK)
+        i = torch.arange(s, e, dtype=torch.int64, device="cuda")
+        keys[s:e] = _u32_from((i * c) & 0xFFFFFFFF)
+        vals[s:e] = _u32_from(i)
+    mp.sort(keys, vals)
+    torch.cuda.synchronize()
+    prev = None
+    for s in range(0, n, CHUNK):
+        e = min(n, s + CHUNK)
+        k = keys[s:e].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        v = vals[s:e].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        assert bool(torch.all(k[1:] > k[:-1])), s
+        if prev is not None:
+            assert int(k[0]) > prev, s
+        prev = int(k[-1])
+        assert torch.equal((v * c) & 0xFFFFFFFF, k), s
+        assert bool(torch.all(v < n)), s
