@@ -405,6 +405,29 @@ def leg_learned(args, ex):
     ds = np.sort(np.random.default_rng(0).integers(0, N + 1, 256)).astype(np.int64)
     got = lp.partition(A, B, dev(ds)).cpu().numpy()
     res["oracle_spot_check_256"] = bool(np.array_equal(got, oracle.partition(Ah, Bh, ds)))
+    # the full f32 merge (Algorithm 1 in two calls) on learned splits of the
+    # 4096-key tile diagonals, against the same on plain splits and against
+    # the persistent merge
+    log("bench: learned: full f32 merge on learned splits")
+    T = 4096
+    tdiag = torch.clamp(torch.arange((N + T - 1) // T + 1, device="cuda", dtype=torch.int64) * T,
+                        max=N)
+    sp_l = torch.empty_like(tdiag)
+    sp_p = torch.empty_like(tdiag)
+    S = torch.empty(N, dtype=torch.float32, device="cuda")
+    t_pl = time_steps(lambda: lp.partition(A, B, tdiag, out=sp_l), 10, 3)
+    t_pp = time_steps(lambda: mp.partition(A, B, tdiag, out=sp_p), 10, 3)
+    t_mt = time_steps(lambda: mp.merge_split(A, B, sp_l, T, out=S), 10, 3)
+    got = S.cpu().numpy()
+    t_ps = time_steps(lambda: mp.merge(A, B, out=S), 10, 3)
+    ref = oracle.merge(Ah, Bh)
+    res["f32_merge_on_learned_splits"] = {
+        "n": N, "tile": T, "tiles": int(tdiag.numel() - 1),
+        "learned_split_ms": round(t_pl, 4), "plain_split_ms": round(t_pp, 4),
+        "tile_merge_ms": round(t_mt, 4), "total_learned_ms": round(t_pl + t_mt, 4),
+        "total_plain_ms": round(t_pp + t_mt, 4), "persistent_merge_ms": round(t_ps, 4),
+        "splits_identical": bool(torch.equal(sp_l, sp_p)),
+        "bit_exact": bool(got.tobytes() == ref.tobytes())}
     ex["learned"] = res
 
 

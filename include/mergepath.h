@@ -109,6 +109,24 @@ mp_status mp_merge(mp_dtype kt, const void *A, int64_t na, const void *B,
                    int64_t nb, void *S, void *stream);
 
 /*
+ * mp_merge_split -- the second step of Algorithm 1 on splits the caller
+ * already has: output tile k, S[k*tile, min((k+1)*tile, na+nb)), is merged
+ * from the pair that a_split[k] and a_split[k+1] cut out (Corollary 6),
+ * one workgroup per tile, tiles independent.
+ *   a_split  ceil((na+nb)/tile) + 1 int64 splits (device) on the diagonals
+ *            min(k*tile, na+nb): what mp_partition or mp_partition_learned
+ *            return for those diagonals.
+ *   tile     2048, 3840 or 4096 outputs per tile (MP_ERR_UNSUPPORTED else).
+ *   S        na+nb keys, must overlap neither input nor a_split.
+ * The result is the merge when the splits are the true ones.  Other split
+ * values give some other output but stay memory-safe: every split is
+ * clamped to its diagonal's extent inside the grid.
+ */
+mp_status mp_merge_split(mp_dtype kt, const void *A, int64_t na, const void *B,
+                         int64_t nb, const int64_t *a_split, int32_t tile, void *S,
+                         void *stream);
+
+/*
  * mp_merge_checksum -- the merge of A and B computed but not written: the
  * runs of section 6 whose merged values go to a local register instead of
  * memory, which isolate reading and comparing from storing.  Every output

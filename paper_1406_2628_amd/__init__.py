@@ -51,6 +51,7 @@ def _declare(L):
         "mp_partition_lanes": ([i32], i32),
         "mp_merge": ([i32, p, i64, p, i64, p, p], i32),
         "mp_merge_checksum": ([i32, p, i64, p, i64, p, p], i32),
+        "mp_merge_split": ([i32, p, i64, p, i64, p, i32, p, p], i32),
         "mp_merge_kv": ([i32, i32, p, p, i64, p, p, i64, p, p, p], i32),
         "mp_merge_batched_workspace_bytes": ([i32, i64, i64], sz),
         "mp_merge_batched": ([i32, p, p, p, p, i64, i64, i64, p, p, sz, p], i32),
@@ -206,6 +207,18 @@ def partition(A: torch.Tensor, B: torch.Tensor, diag: torch.Tensor,
         out = torch.empty(diag.numel(), dtype=torch.int64, device=A.device)
     _check(lib().mp_partition(kt, _ptr(A), A.numel(), _ptr(B), B.numel(), _ptr(diag),
                               diag.numel(), _ptr(out), _stream(A.device)))
+    return out
+
+
+def merge_split(A: torch.Tensor, B: torch.Tensor, a_split: torch.Tensor, tile: int = 4096,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """Merge tile by tile from given splits on the diagonals min(k * tile, N)
+    (ceil(N / tile) + 1 int64 values, as ``partition`` returns them)."""
+    kt = _key_dtype(A, B)
+    if out is None:
+        out = torch.empty(A.numel() + B.numel(), dtype=A.dtype, device=A.device)
+    _check(lib().mp_merge_split(kt, _ptr(A), A.numel(), _ptr(B), B.numel(), _ptr(a_split), tile,
+                                _ptr(out), _stream(A.device)))
     return out
 
 

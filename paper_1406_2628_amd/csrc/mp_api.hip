@@ -247,6 +247,40 @@ mp_status mp_merge(mp_dtype kt, const void *A, int64_t na, const void *B,
                       nullptr, stream);
 }
 
+mp_status mp_merge_split(mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb,
+                         const int64_t *a_split, int32_t tile, void *S, void *stream) {
+  const char *fn = "mp_merge_split";
+  if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported key dtype %d", fn, (int)kt);
+  TileCfg tc{0, 0};
+  if (tile == 4096) tc = {256, 16};
+  else if (tile == 3840) tc = {256, 15};
+  else if (tile == 2048) tc = {256, 8};
+  else return fail(MP_ERR_UNSUPPORTED, "%s: tile must be 2048, 3840 or 4096", fn);
+  const size_t es = dtype_size(kt);
+  mp_status st;
+  if ((st = check_array(A, na, es, "A")) != MP_OK) return st;
+  if ((st = check_array(B, nb, es, "B")) != MP_OK) return st;
+  if (na > INT64_MAX - nb) return fail(MP_ERR_INVALID_ARG, "%s: na + nb overflows", fn);
+  const int64_t n = na + nb;
+  const int64_t n_tiles = (n + tile - 1) / tile;
+  if ((st = check_array(S, n, es, "S")) != MP_OK) return st;
+  if (n > 0 && (st = check_array(a_split, n_tiles + 1, 8, "a_split")) != MP_OK) return st;
+  const Range rs = span(S, n, es);
+  if (overlaps(rs, span(A, na, es)) || overlaps(rs, span(B, nb, es)) ||
+      overlaps(rs, span(a_split, n_tiles + 1, 8)))
+    return fail(MP_ERR_OVERLAP, "%s: S overlaps an input", fn);
+  if (n == 0) return MP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  dispatch_key(kt, [&](auto k) {
+    using K = decltype(k);
+    KernelTimer timer("merge_tiles", s);
+    e = launch_merge_tiles<K>(tc, (const K *)A, nullptr, na, (const K *)B, nullptr, nb, (K *)S,
+                              nullptr, a_split, s);
+  });
+  return e == hipSuccess ? MP_OK : hip_fail(e, "mp_merge_split launch");
+}
+
 mp_status mp_merge_checksum(mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb,
                             uint64_t *checksum, void *stream) {
   const char *fn = "mp_merge_checksum";

@@ -108,11 +108,16 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(
   const int64_t n_all = na + nb;
   const int64_t d0 = tile * T;
   const int64_t d1 = d0 + T < n_all ? d0 + T : n_all;
-  const int64_t a0 = a_split[tile], a1 = a_split[tile + 1];
+  // The splits may come from the caller (mp_merge_split): a0 is kept on the
+  // start diagonal inside the grid and the window width below in its valid
+  // range, so every access stays in bounds whatever the split values.  For
+  // true splits of sorted inputs both clamps change nothing.
+  const int64_t lo0 = d0 > nb ? d0 - nb : 0, hi0 = d0 < na ? d0 : na;
+  int64_t a0 = a_split[tile];
+  a0 = a0 < lo0 ? lo0 : (a0 > hi0 ? hi0 : a0);
+  const int64_t a1 = a_split[tile + 1];
   const int64_t b0 = d0 - a0;
   const int n = (int)(d1 - d0);
-  // For sorted inputs a1 - a0 already lies in this range; the clamp only
-  // keeps every access in bounds when the sortedness precondition is broken.
   int64_t wa64 = a1 - a0;
   const int64_t wa_lo = d1 - nb - a0 > 0 ? d1 - nb - a0 : 0;
   const int64_t wa_hi = na - a0 < (int64_t)n ? na - a0 : (int64_t)n;

@@ -65,6 +65,18 @@ def test_merge_argument_errors(L):
     assert L.mp_merge(MP_U64, a, 1 << 62, b, 1 << 62, s, None) in (INVALID, OVERLAP)
 
 
+def test_merge_split_argument_errors(L):
+    a, b, sp, s = P(0x10000), P(0x20000), P(0x30000), P(0x40000)
+    assert L.mp_merge_split(MP_U32, a, 10, b, 10, sp, 1000, s, None) == UNSUPPORTED
+    assert L.mp_merge_split(99, a, 10, b, 10, sp, 4096, s, None) == UNSUPPORTED
+    assert L.mp_merge_split(MP_U32, a, 10, b, 10, None, 4096, s, None) == INVALID
+    assert L.mp_merge_split(MP_U32, a, 10, b, 10, P(0x30004), 4096, s, None) == INVALID
+    assert L.mp_merge_split(MP_U32, a, 10, b, 10, sp, 4096, None, None) == INVALID
+    assert L.mp_merge_split(MP_U32, a, 10, b, 10, sp, 4096, P(0x30000 - 16), None) == OVERLAP
+    assert L.mp_merge_split(MP_U32, a, 10, b, 10, sp, 4096, P(0x10000 + 4), None) == OVERLAP
+    assert L.mp_merge_split(MP_U32, None, 0, None, 0, None, 4096, None, None) == OK
+
+
 def test_merge_checksum_argument_errors(L):
     a, b, c = P(0x10000), P(0x20000), P(0x30000)
     assert L.mp_merge_checksum(99, a, 10, b, 10, c, None) == UNSUPPORTED

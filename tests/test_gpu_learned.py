@@ -192,6 +192,20 @@ def test_learned_partition_identical(mp, orc, trained):
     _check_identical(mp, orc, lp, A, B, diag)
 
 
+def test_merge_from_learned_splits(mp, orc, trained):
+    """The learned splits on the tile diagonals drive a full merge
+    (mp_merge_split) to the oracle's bits."""
+    from gpu_util import dev, host, first_mismatch
+    lp, _, _, _, n = trained
+    A, B = gen.f32_mixture_pair(n, n, 60)
+    dA, dB = dev(A), dev(B)
+    N = len(A) + len(B)
+    d = np.minimum(np.arange((N + 4095) // 4096 + 1, dtype=np.int64) * 4096, N)
+    sp = lp.partition(dA, dB, dev(d))
+    got = host(mp.merge_split(dA, dB, sp, 4096))
+    assert first_mismatch(got, orc.merge(A, B)) is None
+
+
 def test_forced_fallback_zero_window(mp, orc, trained, tmp_path):
     lp, _, _, _, n = trained
     path = str(tmp_path / "copy.mplp")

@@ -101,6 +101,49 @@ def _position_checksum(S):
         return int(np.sum(bits * np.arange(1, len(S) + 1, dtype=np.uint64), dtype=np.uint64))
 
 
+def _tile_diagonals(n, tile):
+    return np.minimum(np.arange((n + tile - 1) // tile + 1, dtype=np.int64) * tile, n)
+
+
+@pytest.mark.parametrize("tile", [2048, 3840, 4096])
+def test_merge_split_from_partition(mp, orc, tile):
+    """Algorithm 1 in two calls: splits on the tile diagonals, then the tiles
+    merged independently, gives the oracle's merge."""
+    from gpu_util import dev, host, first_mismatch
+    cases = [gen.uniform_pair(100_003, 77_777, 71, dt) for dt in DTYPES]
+    cases += [gen.dups_pair(50_001, 60_007, 72, hi=9), gen.disjoint_pair(40_000, 30_001, 73),
+              gen.uniform_pair(5, 60_000, 74), gen.uniform_pair(0, 1000, 75),
+              gen.uniform_pair(1, 0, 76), gen.uniform_pair(tile, tile, 77)]
+    for A, B in cases:
+        n = len(A) + len(B)
+        d = _tile_diagonals(n, tile)
+        dA, dB = dev(A), dev(B)
+        sp = mp.partition(dA, dB, dev(d))
+        got = host(mp.merge_split(dA, dB, sp, tile))
+        assert first_mismatch(got, orc.merge(A, B)) is None, (A.dtype, len(A), len(B))
+
+
+def test_merge_split_keeps_any_splits_in_bounds(mp, orc):
+    """Split values that are not the true splits (out of range, decreasing,
+    random) give some other output, but every access stays inside the
+    arrays: the kernel clamps each split to its diagonal's extent."""
+    import torch
+    from gpu_util import dev, host
+    A, B = gen.uniform_pair(30_001, 20_011, 78)
+    n = len(A) + len(B)
+    k = (n + 4095) // 4096 + 1
+    g = np.random.default_rng(79)
+    for sp in (np.full(k, 1 << 62, np.int64), np.full(k, -5, np.int64),
+               np.arange(k, dtype=np.int64)[::-1].copy() * 4096, g.integers(-n, 2 * n, k)):
+        out = mp.merge_split(dev(A), dev(B), dev(sp), 4096)
+        torch.cuda.synchronize()
+        assert host(out).shape == (n,)
+    # the true splits still give the merge afterwards
+    d = _tile_diagonals(n, 4096)
+    got = host(mp.merge_split(dev(A), dev(B), mp.partition(dev(A), dev(B), dev(d)), 4096))
+    assert np.array_equal(got, orc.merge(A, B))
+
+
 @pytest.mark.parametrize("cfg", [None, (2, 256, 16, 0, 0), (2, 192, 24, 5, 0), (2, 256, 16, 0, 64)])
 def test_merge_checksum_no_store(mp, orc, cfg):
     """The merge kept in registers (nothing stored) accounts for every output
