@@ -101,8 +101,8 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(
   constexpr int T = NT * VT;
   // slack of VT + 1 slots: the unguarded serial merge may read up to VT
   // positions past the A window end (outputs discarded)
-  __shared__ K keys[T + VT + 1];
-  __shared__ uint32_t vals[KV ? T : 1];
+  __shared__ __attribute__((aligned(16))) K keys[T + VT + 1];
+  __shared__ __attribute__((aligned(16))) uint32_t vals[KV ? T : 1];
   const int tid = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t n_all = na + nb;
@@ -164,9 +164,21 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(
     }
   }
   __syncthreads();
-  for (int i = tid; i < n; i += NT) {
-    S[d0 + i] = keys[i];
-    if constexpr (KV) Sv[d0 + i] = vals[i];
+  // 16-byte nontemporal stores where the tile's output is aligned (every
+  // tile starts at a multiple of T keys), element stores for the rest
+  constexpr int VEC = 16 / (int)sizeof(K);
+  const bool vec = (((uintptr_t)(S + d0) | (KV ? (uintptr_t)(Sv + d0) : 0)) % 16) == 0;
+  const int nv = vec ? n / VEC : 0;
+  for (int v = tid; v < nv; v += NT)
+    __builtin_nontemporal_store(reinterpret_cast<const u32x4 *>(keys)[v],
+                                reinterpret_cast<u32x4 *>(S + d0) + v);
+  for (int i = nv * VEC + tid; i < n; i += NT) S[d0 + i] = keys[i];
+  if constexpr (KV) {
+    const int nv4 = vec ? n / 4 : 0;
+    for (int v = tid; v < nv4; v += NT)
+      __builtin_nontemporal_store(reinterpret_cast<const u32x4 *>(vals)[v],
+                                  reinterpret_cast<u32x4 *>(Sv + d0) + v);
+    for (int i = nv4 * 4 + tid; i < n; i += NT) Sv[d0 + i] = vals[i];
   }
 }
 
