@@ -57,6 +57,8 @@ def _declare(lib):
         getattr(lib, f"oracle_partition_{n}").argtypes = [p, i64, p, i64, p, i64, p]
         getattr(lib, f"oracle_sort_{n}").argtypes = [p, p, i64]
         getattr(lib, f"oracle_merge_batched_{n}").argtypes = [p, p, p, p, i64, p]
+        getattr(lib, f"oracle_set_op_{n}").argtypes = [ctypes.c_int, p, i64, p, i64, p]
+        getattr(lib, f"oracle_set_op_{n}").restype = i64
     return lib
 
 
@@ -132,3 +134,18 @@ def merge_batched(A, a_off, B, b_off, lib=None):
     if rc != 0:
         raise ValueError(f"oracle_merge_batched failed ({rc})")
     return S
+
+
+SET_OPS = {"intersection": 0, "union": 1, "difference": 2, "symmetric_difference": 3}
+
+
+def set_op(op: str, A, B, lib=None):
+    """Multiset intersection / union / difference / symmetric difference of
+    sorted A and B, in merged order (A's copies before B's)."""
+    lib = lib or load()
+    A = np.ascontiguousarray(A)
+    B = np.ascontiguousarray(B)
+    n = _key_name(A, B)
+    S = np.empty(len(A) + len(B), dtype=A.dtype)
+    k = getattr(lib, f"oracle_set_op_{n}")(SET_OPS[op], _ptr(A), len(A), _ptr(B), len(B), _ptr(S))
+    return S[:k].copy()

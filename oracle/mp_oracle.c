@@ -16,7 +16,9 @@
  *   - sort:       bottom-up merge sort, log2 N rounds of pairwise merges
  *                 (section 1; section 3, parallel merge sort);
  *   - batched:    independent merges of many (A_k, B_k) pairs written back to
- *                 back (Corollary 6 applied pair by pair).
+ *                 back (Corollary 6 applied pair by pair);
+ *   - set ops:    the multiset intersection, union, difference and symmetric
+ *                 difference walked like the merge (matched equal heads).
  *
  * Key types: u32 and u64 compare unsigned, i32 signed, f32 with IEEE '<'/'>'
  * (so -0.0 and +0.0 tie, and the tie rule decides which bit pattern is output).
@@ -186,12 +188,44 @@ static int cmp_diag(const void *x, const void *y) {
     return 0;                                                                  \
   }
 
+/*
+ * Multiset operations on sorted inputs, walked like the merge (op 0 =
+ * intersection, 1 = union, 2 = difference A minus B, 3 = symmetric
+ * difference).  Standing at (i, j): the smaller head is unmatched and moves
+ * on alone; equal heads are a matched pair and both move on.  Union keeps
+ * every unmatched head and one key (A's) of each matched pair; intersection
+ * keeps A's key of each matched pair; difference keeps unmatched A heads;
+ * symmetric difference keeps every unmatched head.  So a value found m
+ * times in A and n times in B comes out min(m, n), max(m, n), max(m - n, 0)
+ * and |m - n| times, A's copies before B's.  Returns the output count.
+ */
+#define DEFINE_SETOP(T, NAME)                                                  \
+  int64_t oracle_set_op_##NAME(int op, const T *A, int64_t na, const T *B,     \
+                               int64_t nb, T *S) {                             \
+    int64_t i = 0, j = 0, k = 0;                                               \
+    while (i < na || j < nb) {                                                 \
+      if (j == nb || (i < na && A[i] < B[j])) {                                \
+        if (op != 0) S[k++] = A[i];                                            \
+        ++i;                                                                   \
+      } else if (i == na || B[j] < A[i]) {                                     \
+        if (op == 1 || op == 3) S[k++] = B[j];                                 \
+        ++j;                                                                   \
+      } else {                                                                 \
+        if (op == 0 || op == 1) S[k++] = A[i];                                 \
+        ++i;                                                                   \
+        ++j;                                                                   \
+      }                                                                        \
+    }                                                                          \
+    return k;                                                                  \
+  }
+
 #define DEFINE_ALL(T, NAME)                                                    \
   DEFINE_MERGE(T, NAME)                                                        \
   DEFINE_MERGE_KV(T, NAME)                                                     \
   DEFINE_PARTITION(T, NAME)                                                    \
   DEFINE_SORT(T, NAME)                                                         \
-  DEFINE_BATCHED(T, NAME)
+  DEFINE_BATCHED(T, NAME)                                                      \
+  DEFINE_SETOP(T, NAME)
 
 DEFINE_ALL(uint32_t, u32)
 DEFINE_ALL(int32_t, i32)
