@@ -109,6 +109,32 @@ mp_status mp_merge(mp_dtype kt, const void *A, int64_t na, const void *B,
                    int64_t nb, void *S, void *stream);
 
 /*
+ * mp_set_op -- multiset operations on sorted A and B through the same
+ * partition: the merge's output tiles are cut by Algorithm 2 on their
+ * diagonals and each tile's pair is processed independently (Corollary 6),
+ * keeping or dropping each merged key.
+ *   op     0 intersection, 1 union, 2 difference (A minus B),
+ *          3 symmetric difference.  A value found m times in A and n times
+ *          in B comes out min(m, n), max(m, n), max(m - n, 0) and |m - n|
+ *          times, in sorted order with A's copies before B's; equal keys
+ *          pair front to front, so intersection keeps A's first copies,
+ *          difference A's last ones, union and symmetric difference the
+ *          longer run's last excess copies (the rules of the C++ standard
+ *          library's set algorithms).
+ *   S      room for na keys (intersection, difference) or na + nb keys
+ *          (union, symmetric difference); the first *count are written.
+ *   count  one int64 in device memory (8-byte aligned): the output length,
+ *          written when the work runs.
+ *   ws     device workspace of at least mp_set_op_workspace_bytes(na, nb)
+ *          bytes, 8-byte aligned.
+ * Neither S, count nor ws may overlap an input or each other.
+ */
+size_t mp_set_op_workspace_bytes(int64_t na, int64_t nb);
+mp_status mp_set_op(int32_t op, mp_dtype kt, const void *A, int64_t na, const void *B,
+                    int64_t nb, void *S, int64_t *count, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/*
  * mp_merge_split -- the second step of Algorithm 1 on splits the caller
  * already has: output tile k, S[k*tile, min((k+1)*tile, na+nb)), is merged
  * from the pair that a_split[k] and a_split[k+1] cut out (Corollary 6),

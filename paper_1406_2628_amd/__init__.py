@@ -52,6 +52,8 @@ def _declare(L):
         "mp_merge": ([i32, p, i64, p, i64, p, p], i32),
         "mp_merge_checksum": ([i32, p, i64, p, i64, p, p], i32),
         "mp_merge_split": ([i32, p, i64, p, i64, p, i32, p, p], i32),
+        "mp_set_op_workspace_bytes": ([i64, i64], ctypes.c_size_t),
+        "mp_set_op": ([i32, i32, p, i64, p, i64, p, p, p, ctypes.c_size_t, p], i32),
         "mp_merge_kv": ([i32, i32, p, p, i64, p, p, i64, p, p, p], i32),
         "mp_merge_batched_workspace_bytes": ([i32, i64, i64], sz),
         "mp_merge_batched": ([i32, p, p, p, p, i64, i64, i64, p, p, sz, p], i32),
@@ -208,6 +210,32 @@ def partition(A: torch.Tensor, B: torch.Tensor, diag: torch.Tensor,
     _check(lib().mp_partition(kt, _ptr(A), A.numel(), _ptr(B), B.numel(), _ptr(diag),
                               diag.numel(), _ptr(out), _stream(A.device)))
     return out
+
+
+SET_OPS = {"intersection": 0, "union": 1, "difference": 2, "symmetric_difference": 3}
+
+
+def set_op(op: str, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,
+           count: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+           sync: bool = True):
+    """Multiset intersection / union / difference / symmetric_difference of
+    sorted A and B.  With sync (default) returns the output trimmed to its
+    length; otherwise returns (out, count) with count an int64 device scalar."""
+    kt = _key_dtype(A, B)
+    code = SET_OPS[op]
+    cap = A.numel() if code in (0, 2) else A.numel() + B.numel()
+    if out is None:
+        out = torch.empty(max(cap, 1), dtype=A.dtype, device=A.device)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=A.device)
+    need = lib().mp_set_op_workspace_bytes(A.numel(), B.numel())
+    if ws is None:
+        ws = torch.empty(max(need, 8), dtype=torch.uint8, device=A.device)
+    _check(lib().mp_set_op(code, kt, _ptr(A), A.numel(), _ptr(B), B.numel(), _ptr(out), _ptr(count),
+                           _ptr(ws), ws.numel(), _stream(A.device)))
+    if not sync:
+        return out, count
+    return out[: int(count.item())]
 
 
 def merge_split(A: torch.Tensor, B: torch.Tensor, a_split: torch.Tensor, tile: int = 4096,

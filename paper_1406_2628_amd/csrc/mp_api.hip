@@ -247,6 +247,50 @@ mp_status mp_merge(mp_dtype kt, const void *A, int64_t na, const void *B,
                       nullptr, stream);
 }
 
+size_t mp_set_op_workspace_bytes(int64_t na, int64_t nb) {
+  if (na < 0 || nb < 0 || na > INT64_MAX - nb) return 0;
+  return (size_t)(3 * (setop_tiles(na + nb) + 1)) * sizeof(int64_t);
+}
+
+mp_status mp_set_op(int32_t op, mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb,
+                    void *S, int64_t *count, void *ws, size_t ws_bytes, void *stream) {
+  const char *fn = "mp_set_op";
+  if (op < 0 || op > 3) return fail(MP_ERR_INVALID_ARG, "%s: op must be 0, 1, 2 or 3", fn);
+  if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported key dtype %d", fn, (int)kt);
+  const size_t es = dtype_size(kt);
+  mp_status st;
+  if ((st = check_array(A, na, es, "A")) != MP_OK) return st;
+  if ((st = check_array(B, nb, es, "B")) != MP_OK) return st;
+  if (na > INT64_MAX - nb) return fail(MP_ERR_INVALID_ARG, "%s: na + nb overflows", fn);
+  if (!count || (uintptr_t)count % 8)
+    return fail(MP_ERR_INVALID_ARG, "%s: count must be an 8-byte aligned device pointer", fn);
+  // largest possible output: every key of A (intersection, difference) or of both
+  const int64_t cap = (op == 0 || op == 2) ? na : na + nb;
+  if ((st = check_array(S, cap, es, "S")) != MP_OK) return st;
+  const size_t need = mp_set_op_workspace_bytes(na, nb);
+  if (!ws || ws_bytes < need)
+    return fail(MP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+  if ((uintptr_t)ws % 8) return fail(MP_ERR_INVALID_ARG, "%s: workspace not 8-byte aligned", fn);
+  const Range rs = span(S, cap, es), rw = span(ws, (int64_t)need, 1), rc = span(count, 1, 8);
+  const Range ra = span(A, na, es), rb = span(B, nb, es);
+  if (overlaps(rs, ra) || overlaps(rs, rb) || overlaps(rs, rw) || overlaps(rs, rc) ||
+      overlaps(rw, ra) || overlaps(rw, rb) || overlaps(rw, rc) || overlaps(rc, ra) ||
+      overlaps(rc, rb))
+    return fail(MP_ERR_OVERLAP, "%s: S, count, workspace and the inputs must not overlap", fn);
+  hipStream_t s = (hipStream_t)stream;
+  if (na + nb == 0) {
+    const hipError_t e = hipMemsetAsync(count, 0, sizeof(int64_t), s);
+    return e == hipSuccess ? MP_OK : hip_fail(e, "mp_set_op");
+  }
+  hipError_t e = hipSuccess;
+  dispatch_key(kt, [&](auto k) {
+    using K = decltype(k);
+    KernelTimer timer("set_op", s);
+    e = launch_set_op<K>(op, (const K *)A, na, (const K *)B, nb, (K *)S, count, (int64_t *)ws, s);
+  });
+  return e == hipSuccess ? MP_OK : hip_fail(e, "mp_set_op launch");
+}
+
 mp_status mp_merge_split(mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb,
                          const int64_t *a_split, int32_t tile, void *S, void *stream) {
   const char *fn = "mp_merge_split";

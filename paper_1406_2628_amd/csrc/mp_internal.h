@@ -83,6 +83,14 @@ template <typename K>
 hipError_t launch_merge_checksum(StreamCfg cfg, const K *A, int64_t na, const K *B, int64_t nb,
                                  unsigned long long *checksum, hipStream_t s);
 
+// Multiset operation (0 intersection, 1 union, 2 difference, 3 symmetric
+// difference) of sorted A and B into S; *count (device) receives the output
+// length.  ws: 3 * (setop_tiles(na + nb) + 1) int64 of device workspace.
+int64_t setop_tiles(int64_t n);
+template <typename K>
+hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb, K *S,
+                         int64_t *count, int64_t *ws, hipStream_t s);
+
 // Batched merge of CSR-concatenated pairs (persistent, one launch).
 template <typename K>
 hipError_t launch_merge_batched(StreamCfg cfg, const K *A, const int64_t *a_off,

@@ -1,0 +1,283 @@
+// Multiset operations on two sorted inputs through the same partition: the
+// output tiles of the merge are cut by splits on their diagonals (Algorithm
+// 2) and each tile's pair is processed independently (Corollary 6), here
+// keeping or dropping each merged key instead of writing all of them.
+//
+// In the stable merge the copies of a value sit together, A's m copies
+// first, then B's n.  Pairing equal keys front to front:
+//   - A's copy of rank k (k counted from the start of its run in A) is
+//     matched when B holds more than k copies, i.e. when B[lb_B + k] equals
+//     it, where lb_B, the start of the value's run in B, is exactly the
+//     path's b when that A copy is taken (ties take A, so no copy of the
+//     value from B precedes it);
+//   - B's copy of rank k is matched when A holds more than k copies, i.e.
+//     when A[ub_A - 1 - k] equals it, where ub_A is the path's a when that B
+//     copy is taken (all of A's copies precede it).
+// Intersection keeps matched A copies; union keeps every A copy and the
+// unmatched B copies; difference keeps the unmatched A copies; symmetric
+// difference keeps the unmatched copies of both.
+//
+// The rank of the first A (and B) copy a lane takes comes from a lower-bound
+// search in the tile's LDS window; only the window's first value can have its
+// run start before the window, and wave 0 finds that start in global memory
+// once per tile.  Ranks then advance along the lane's serial merge.
+//
+// Two launches of the same tile kernel: the first counts each tile's kept
+// keys, a one-workgroup scan turns the counts into output offsets (and the
+// total), the second writes the kept keys, compacted through LDS.
+#include <type_traits>
+
+#include "mp_device.h"
+#include "mp_internal.h"
+
+namespace mp {
+
+constexpr int kSetNT = 256, kSetVT = 16, kSetT = kSetNT * kSetVT;
+
+template <typename K>
+__device__ __forceinline__ bool key_eq(K x, K y) {
+  return !(x < y) && !(y < x);
+}
+
+// First index i in [lo, hi) with pred(i) true (pred monotone false -> true),
+// hi if none; found by the 64 lanes of the calling wavefront, 64 probes per
+// round.  Every lane returns the result.
+template <typename P>
+__device__ int64_t wave_first_true(int64_t lo, int64_t hi, P pred) {
+  const int lane = threadIdx.x & 63;
+  while (lo < hi) {
+    const int64_t span = hi - lo;
+    if (span <= 64) {
+      const uint64_t m = __ballot(lane < span && pred(lo + lane));
+      return m ? lo + (int64_t)(__ffsll((long long)m) - 1) : hi;
+    }
+    const int64_t p = lo + ((int64_t)(lane + 1) * span) / 65;
+    const uint64_t m = __ballot(pred(p));
+    if (m == 0) {
+      lo = lo + ((int64_t)64 * span) / 65 + 1;
+    } else {
+      const int f = __ffsll((long long)m) - 1;
+      const int64_t pf = lo + ((int64_t)(f + 1) * span) / 65;
+      lo = f == 0 ? lo : lo + ((int64_t)f * span) / 65 + 1;
+      hi = pf;
+    }
+  }
+  return lo;
+}
+
+// OP: 0 intersection, 1 union, 2 difference, 3 symmetric difference.
+// EMIT = false: counts[tile] = keys kept; true: writes them to S at
+// offsets[tile].
+template <typename K, int OP, bool EMIT>
+__global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
+    const K *__restrict__ A, int64_t na, const K *__restrict__ B, int64_t nb,
+    const int64_t *__restrict__ a_split, int64_t *__restrict__ counts,
+    const int64_t *__restrict__ offsets, K *__restrict__ S) {
+  constexpr int NT = kSetNT, VT = kSetVT, T = kSetT;
+  __shared__ K keys[T + VT + 1];
+  __shared__ int s_cnt[NT];
+  __shared__ int64_t s_lb[2];
+  const int tid = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t N = na + nb;
+  const int64_t d0 = tile * T;
+  const int64_t d1 = d0 + T < N ? d0 + T : N;
+  const int n = (int)(d1 - d0);
+  // the tile's pair (splits from the grid search; the clamps keep every
+  // access in bounds as in the merge's per-tile kernel)
+  const int64_t lo0 = d0 > nb ? d0 - nb : 0, hi0 = d0 < na ? d0 : na;
+  int64_t a0 = a_split[tile];
+  a0 = a0 < lo0 ? lo0 : (a0 > hi0 ? hi0 : a0);
+  const int64_t b0 = d0 - a0;
+  int64_t wa64 = a_split[tile + 1] - a0;
+  const int64_t wa_lo = d1 - nb - a0 > 0 ? d1 - nb - a0 : 0;
+  const int64_t wa_hi = na - a0 < (int64_t)n ? na - a0 : (int64_t)n;
+  wa64 = wa64 < wa_lo ? wa_lo : (wa64 > wa_hi ? wa_hi : wa64);
+  const int wa = (int)wa64, wb = n - wa;
+  for (int i = tid; i < wa; i += NT) keys[i] = A[a0 + i];
+  for (int i = tid; i < wb; i += NT) keys[wa + i] = B[b0 + i];
+  // run starts of the window's first A and first B value (global search only
+  // when the run reaches back past the window)
+  if (tid < 64) {
+    int64_t lbA = a0, lbB = b0;
+    if (wa > 0 && a0 > 0) {
+      const K v = A[a0];
+      if (key_eq(A[a0 - 1], v))
+        lbA = wave_first_true(0, a0, [&](int64_t i) { return !(A[i] < v); });
+    }
+    if (wb > 0 && b0 > 0) {
+      const K v = B[b0];
+      if (key_eq(B[b0 - 1], v))
+        lbB = wave_first_true(0, b0, [&](int64_t i) { return !(B[i] < v); });
+    }
+    if (tid == 0) {
+      s_lb[0] = lbA;
+      s_lb[1] = lbB;
+    }
+  }
+  __syncthreads();
+
+  // this lane's split at local diagonal tid * VT
+  const int dl = tid * VT < n ? tid * VT : n;
+  int lo, hi;
+  diag_range<int>(dl, wa, wb, lo, hi);
+  const int a = split_search<int>(
+      dl, lo, hi, [&](int i) { return keys[i]; }, [&](int j) { return keys[wa + j]; });
+  int ai = a, bi = wa + dl - a;  // LDS positions
+  const int steps = n - dl < VT ? n - dl : VT;
+  // ranks of the first A and B copies this lane takes
+  int64_t kA = 0, kB = 0;
+  K lastA{}, lastB{};
+  if (ai < wa) {
+    lastA = keys[ai];
+    int l = 0, h = ai;  // first position in [0, ai] holding lastA
+    while (l < h) {
+      const int m = (l + h) >> 1;
+      if (keys[m] < lastA) l = m + 1; else h = m;
+    }
+    kA = (a0 + ai) - (l > 0 ? a0 + l : s_lb[0]);
+  }
+  if (bi < n) {
+    lastB = keys[bi];
+    int l = wa, h = bi;
+    while (l < h) {
+      const int m = (l + h) >> 1;
+      if (keys[m] < lastB) l = m + 1; else h = m;
+    }
+    kB = (b0 + (bi - wa)) - (l > wa ? b0 + (l - wa) : s_lb[1]);
+  }
+
+  K out[VT];
+  uint32_t keep = 0;
+#pragma unroll
+  for (int s = 0; s < VT; ++s) {
+    if (s < steps) {
+      const bool take_b = (bi < n) && (ai >= wa || keys[bi] < keys[ai]);
+      if (!take_b) {
+        const K v = keys[ai];
+        if (!key_eq(v, lastA)) {
+          kA = 0;
+          lastA = v;
+        }
+        // matched: B[lb_B + k] == v, lb_B = the path's b here
+        const int64_t jb = b0 + (bi - wa) + kA;
+        bool m = false;
+        if (jb < nb) m = key_eq(jb - b0 < wb ? keys[wa + (int)(jb - b0)] : B[jb], v);
+        out[s] = v;
+        if (OP == 1 || (OP == 0 ? m : !m)) keep |= 1u << s;
+        ++kA;
+        ++ai;
+      } else {
+        const K v = keys[bi];
+        if (!key_eq(v, lastB)) {
+          kB = 0;
+          lastB = v;
+        }
+        // matched: A[ub_A - 1 - k] == v, ub_A = the path's a here
+        const int64_t ia = a0 + ai - 1 - kB;
+        bool m = false;
+        if (ia >= 0) m = key_eq(ia >= a0 ? keys[(int)(ia - a0)] : A[ia], v);
+        out[s] = v;
+        if ((OP == 1 || OP == 3) && !m) keep |= 1u << s;
+        ++kB;
+        ++bi;
+      }
+    }
+  }
+
+  // exclusive prefix of the lanes' kept counts (Hillis-Steele in LDS)
+  const int c = __popc(keep);
+  s_cnt[tid] = c;
+  __syncthreads();
+  for (int o = 1; o < NT; o <<= 1) {
+    const int x = tid >= o ? s_cnt[tid - o] : 0;
+    __syncthreads();
+    s_cnt[tid] += x;
+    __syncthreads();
+  }
+  const int incl = s_cnt[tid];
+  const int total = s_cnt[NT - 1];
+  if constexpr (!EMIT) {
+    if (tid == 0) counts[tile] = total;
+  } else {
+    // compact through LDS (the windows are no longer read), then store
+    int pos = incl - c;
+#pragma unroll
+    for (int s = 0; s < VT; ++s)
+      if ((keep >> s) & 1u) keys[pos++] = out[s];
+    __syncthreads();
+    const int64_t base = offsets[tile];
+    for (int i = tid; i < total; i += NT) S[base + i] = keys[i];
+  }
+}
+
+// Exclusive scan of n counts into offsets[0..n] (offsets[n] = total, also
+// written to *total): one workgroup of 1024 lanes, each summing a contiguous
+// share, then a scan of the shares.
+__global__ __launch_bounds__(1024) void setop_scan_kernel(const int64_t *__restrict__ counts,
+                                                          int64_t n, int64_t *__restrict__ offsets,
+                                                          int64_t *__restrict__ total) {
+  __shared__ int64_t s[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t lo = tid * per < n ? tid * per : n;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  int64_t sum = 0;
+  for (int64_t i = lo; i < hi; ++i) sum += counts[i];
+  s[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t x = tid >= o ? s[tid - o] : 0;
+    __syncthreads();
+    s[tid] += x;
+    __syncthreads();
+  }
+  int64_t run = s[tid] - sum;
+  for (int64_t i = lo; i < hi; ++i) {
+    offsets[i] = run;
+    run += counts[i];
+  }
+  if (tid == 1023) {
+    offsets[n] = s[1023];
+    *total = s[1023];
+  }
+}
+
+int64_t setop_tiles(int64_t n) { return (n + kSetT - 1) / kSetT; }
+
+template <typename K>
+hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb, K *S,
+                         int64_t *count, int64_t *ws, hipStream_t s) {
+  const int64_t n_tiles = setop_tiles(na + nb);
+  int64_t *splits = ws, *counts = ws + (n_tiles + 1), *offsets = counts + (n_tiles + 1);
+  hipError_t e = launch_partition<K>(A, na, B, nb, nullptr, kSetT, n_tiles + 1, splits, s);
+  if (e != hipSuccess) return e;
+  auto run = [&](auto opc) {
+    constexpr int OP = decltype(opc)::value;
+    hipLaunchKernelGGL((setop_tile_kernel<K, OP, false>), dim3((unsigned)n_tiles), dim3(kSetNT),
+                       0, s, A, na, B, nb, splits, counts, offsets, S);
+    hipLaunchKernelGGL(setop_scan_kernel, dim3(1), dim3(1024), 0, s, counts, n_tiles, offsets,
+                       count);
+    hipLaunchKernelGGL((setop_tile_kernel<K, OP, true>), dim3((unsigned)n_tiles), dim3(kSetNT),
+                       0, s, A, na, B, nb, splits, counts, offsets, S);
+  };
+  switch (op) {
+    case 0: run(std::integral_constant<int, 0>()); break;
+    case 1: run(std::integral_constant<int, 1>()); break;
+    case 2: run(std::integral_constant<int, 2>()); break;
+    case 3: run(std::integral_constant<int, 3>()); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#define MP_INSTANTIATE(K)                                                               \
+  template hipError_t launch_set_op<K>(int, const K *, int64_t, const K *, int64_t, K *, \
+                                       int64_t *, int64_t *, hipStream_t);
+MP_INSTANTIATE(uint32_t)
+MP_INSTANTIATE(int32_t)
+MP_INSTANTIATE(uint64_t)
+MP_INSTANTIATE(float)
+#undef MP_INSTANTIATE
+
+}  // namespace mp

@@ -65,6 +65,21 @@ def test_merge_argument_errors(L):
     assert L.mp_merge(MP_U64, a, 1 << 62, b, 1 << 62, s, None) in (INVALID, OVERLAP)
 
 
+def test_set_op_argument_errors(L):
+    a, b, s, c, ws = P(0x10000), P(0x20000), P(0x30000), P(0x40000), P(0x50000)
+    need = L.mp_set_op_workspace_bytes(10, 10)
+    assert need >= 3 * 2 * 8
+    assert L.mp_set_op(4, MP_U32, a, 10, b, 10, s, c, ws, need, None) == INVALID
+    assert L.mp_set_op(0, 99, a, 10, b, 10, s, c, ws, need, None) == UNSUPPORTED
+    assert L.mp_set_op(0, MP_U32, a, 10, b, 10, s, None, ws, need, None) == INVALID
+    assert L.mp_set_op(0, MP_U32, a, 10, b, 10, s, P(0x40004), ws, need, None) == INVALID
+    assert L.mp_set_op(0, MP_U32, a, 10, b, 10, s, c, ws, need - 8, None) == WORKSPACE
+    assert L.mp_set_op(0, MP_U32, a, 10, b, 10, s, c, None, need, None) == WORKSPACE
+    assert L.mp_set_op(1, MP_U32, a, 10, b, 10, P(0x20000 - 40), c, ws, need, None) == OVERLAP
+    assert L.mp_set_op(0, MP_U32, a, 10, b, 10, s, P(0x30000 + 8), ws, need, None) == OVERLAP
+    assert L.mp_set_op(0, MP_U32, a, 10, b, 10, s, c, P(0x40000), need, None) == OVERLAP
+
+
 def test_merge_split_argument_errors(L):
     a, b, sp, s = P(0x10000), P(0x20000), P(0x30000), P(0x40000)
     assert L.mp_merge_split(MP_U32, a, 10, b, 10, sp, 1000, s, None) == UNSUPPORTED

@@ -1,0 +1,81 @@
+"""GPU parity of mp_set_op (multiset operations through the partition)
+against the oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import mp_inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+OPS = ["intersection", "union", "difference", "symmetric_difference"]
+DTYPES = [gen.U32, gen.I32, gen.U64, gen.F32]
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1406_2628_amd as mp
+    mp.lib()
+    return mp
+
+
+def _check(mp, orc, op, A, B):
+    from gpu_util import dev, host
+    got = host(mp.set_op(op, dev(A), dev(B)))
+    want = orc.set_op(op, A, B)
+    assert got.dtype == want.dtype and got.tobytes() == want.tobytes(), (op, len(A), len(B), len(got), len(want))
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dt", DTYPES)
+def test_set_op_uniform_and_dups(mp, orc, op, dt):
+    # distinct-ish keys, few matches; and heavy duplicates, many matches
+    _check(mp, orc, op, *gen.uniform_pair(100_003, 77_777, 81, dt))
+    g = np.random.default_rng(82)
+    npd = gen.NP_DTYPE[dt]
+    for hi in (3, 50, 5000):
+        A = np.sort(g.integers(0, hi, 90_001)).astype(npd)
+        B = np.sort(g.integers(0, hi, 60_007)).astype(npd)
+        _check(mp, orc, op, A, B)
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_set_op_edges(mp, orc, op):
+    g = np.random.default_rng(83)
+    A = np.sort(g.integers(0, 1 << 20, 50_000)).astype(np.uint32)
+    cases = [(A, A.copy()),                                    # identical
+             (A, (A + (1 << 21)).astype(np.uint32)),           # disjoint, B above
+             ((A + (1 << 21)).astype(np.uint32), A),           # disjoint, A above
+             (A, A[:0]), (A[:0], A), (A[:1], A[:1]), (A[:0], A[:0]),
+             (np.full(20_000, 7, np.uint32), np.full(30_000, 7, np.uint32)),   # one long run
+             (np.full(30_000, 7, np.uint32), np.full(9_000, 7, np.uint32)),
+             (np.repeat(np.arange(100, dtype=np.uint32), 97), np.repeat(np.arange(50, 150, dtype=np.uint32), 61)),
+             (np.array([0, 0xFFFFFFFF], np.uint32), np.array([0xFFFFFFFF] * 3, np.uint32))]
+    for A_, B_ in cases:
+        _check(mp, orc, op, A_, B_)
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_set_op_signed_zeros_and_mixture(mp, orc, op):
+    """Equal keys with different bits: which copies are kept must match."""
+    A, B = gen.f32_mixture_pair(120_000, 90_001, 84)
+    _check(mp, orc, op, A, B)
+    z = np.array([-0.0, 0.0], np.float32)
+    g = np.random.default_rng(85)
+    A = np.sort(g.choice(z, 10_000)).astype(np.float32)
+    A = np.concatenate([A, np.float32([1.0] * 5)])
+    B = np.concatenate([g.choice(z, 17_000).astype(np.float32), np.float32([1.0] * 9)])
+    _check(mp, orc, op, A, B)
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_set_op_runs_across_many_tiles(mp, orc, op):
+    """Runs of equal keys longer than a tile, starting anywhere: the global
+    run-start search of each tile."""
+    g = np.random.default_rng(86)
+    vals = np.sort(g.choice(1 << 30, 40, replace=False)).astype(np.uint32)
+    A = np.sort(g.choice(vals, 400_000)).astype(np.uint32)
+    B = np.sort(g.choice(vals, 300_001)).astype(np.uint32)
+    _check(mp, orc, op, A, B)
