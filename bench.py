@@ -10,7 +10,8 @@ kernel timed with HIP events that the library records on its launch stream,
 the single-core oracle baseline timed on the host, the same merge kept in
 registers (nothing stored), and under "extras" the other workloads: a small
 cache-resident merge (hot and cold), key-value merges, merge sort, batched
-merge and the learned split predictor against the plain split search.  Every output is checked
+merge, the learned split predictor against the plain split search, and the
+multiset operations.  Every output is checked
 (bit-exact against the oracle, or for the 2^28 sort against numpy's sort,
 which the oracle's own tests pin).
 
@@ -31,7 +32,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gkeys/s merged & % HBM peak (2^28+2^28 u32); learned vs bsearch split time"
-LEGS = ("headline", "small", "kv", "sort", "batched", "learned")
+LEGS = ("headline", "small", "kv", "sort", "batched", "learned", "setops")
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "merge_stream_u32_2p28.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1406_2628_amd", "csrc", f)
                   for f in ("mp_stream_impl.h", "mp_device.h")]
@@ -235,6 +236,39 @@ def leg_small(args, ex):
     ex["small"] = {"n": 2 * n, "hot_us": round(hot * 1e3, 2), "cold_us": round(cold * 1e3, 2),
                    "hot_Gkeys_s": round(2 * n / hot / 1e6, 1),
                    "cold_Gkeys_s": round(2 * n / cold / 1e6, 1), "bit_exact": ok}
+
+
+# ---------------------------------------------------------------------------
+def leg_setops(args, ex):
+    """Multiset operations on 2^28 + 2^28 sorted u32 keys drawn from [0, 2^29)
+    (about 40% of A's keys find a partner in B), seed 91."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1406_2628_amd as mp
+    n = 1 << args.log2n
+    log(f"bench: set operations 2^{args.log2n}+2^{args.log2n} u32")
+    g = np.random.default_rng(91)
+    A = np.sort(g.integers(0, 2 * n, n, dtype=np.uint32))
+    B = np.sort(g.integers(0, 2 * n, n, dtype=np.uint32))
+    dA, dB = dev(A), dev(B)
+    out = torch.empty(2 * n, dtype=torch.uint32, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    ws = torch.empty(mp.lib().mp_set_op_workspace_bytes(n, n), dtype=torch.uint8, device="cuda")
+    res = {"n_per_input": n}
+    for op in ("intersection", "union", "difference", "symmetric_difference"):
+        ms = time_steps(lambda: mp.set_op(op, dA, dB, out=out, count=cnt, ws=ws, sync=False),
+                        max(3, args.steps // 2), 2)
+        k = int(cnt.item())
+        got = out[:k].cpu().numpy()
+        want = oracle.set_op(op, A, B)
+        # fewest bytes: each input key read once, each kept key written once
+        bytes_ = (2 * n + k) * 4
+        res[op] = {"ms": round(ms, 4), "out": k, "Gkeys_in_s": round(2 * n / ms / 1e6, 1),
+                   "hbm_frac_min_bytes": round(bytes_ / ms / 1e6 / HBM_PEAK_GBS, 4),
+                   "bit_exact": bool(got.tobytes() == want.tobytes())}
+    ex["setops"] = res
 
 
 # ---------------------------------------------------------------------------
@@ -457,7 +491,7 @@ def main():
     leg_headline(args, out)
     ex = {}
     for name, fn in (("small", leg_small), ("kv", leg_kv), ("sort", leg_sort),
-                     ("batched", leg_batched), ("learned", leg_learned)):
+                     ("batched", leg_batched), ("learned", leg_learned), ("setops", leg_setops)):
         if name in legs:
             fn(args, ex)
             torch.cuda.empty_cache()

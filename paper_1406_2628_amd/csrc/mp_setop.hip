@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     const int64_t *__restrict__ offsets, K *__restrict__ S) {
   constexpr int NT = kSetNT, VT = kSetVT, T = kSetT;
   __shared__ K keys[T + VT + 1];
-  __shared__ int s_cnt[NT];
+  __shared__ int s_cnt[NT / 64];
   __shared__ int64_t s_lb[2];
   const int tid = threadIdx.x;
   const int64_t tile = blockIdx.x;
@@ -185,18 +185,25 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     }
   }
 
-  // exclusive prefix of the lanes' kept counts (Hillis-Steele in LDS)
+  // prefix of the lanes' kept counts: a shuffle scan inside each wavefront,
+  // then the wavefront totals through LDS
   const int c = __popc(keep);
-  s_cnt[tid] = c;
-  __syncthreads();
-  for (int o = 1; o < NT; o <<= 1) {
-    const int x = tid >= o ? s_cnt[tid - o] : 0;
-    __syncthreads();
-    s_cnt[tid] += x;
-    __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
+  int incl = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
   }
-  const int incl = s_cnt[tid];
-  const int total = s_cnt[NT - 1];
+  if (lane == 63) s_cnt[wave] = incl;
+  __syncthreads();
+  int total = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const int t = s_cnt[w];
+    incl += w < wave ? t : 0;
+    total += t;
+  }
   if constexpr (!EMIT) {
     if (tid == 0) counts[tile] = total;
   } else {
