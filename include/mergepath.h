@@ -124,7 +124,10 @@ mp_status mp_merge(mp_dtype kt, const void *A, int64_t na, const void *B,
  *   S      room for na keys (intersection, difference) or na + nb keys
  *          (union, symmetric difference); the first *count are written.
  *   count  one int64 in device memory (8-byte aligned): the output length,
- *          written when the work runs.
+ *          written when the work runs.  One pass: each tile finds its output
+ *          offset by looking back over the tiles before it (tiles are taken
+ *          in the order workgroups start, so every wait ends; a bound on the
+ *          polls backs that up, and should it ever trip, count is -1).
  *   ws     device workspace of at least mp_set_op_workspace_bytes(na, nb)
  *          bytes, 8-byte aligned.
  * Neither S, count nor ws may overlap an input or each other.

@@ -235,7 +235,10 @@ def set_op(op: str, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None =
                            _ptr(ws), ws.numel(), _stream(A.device)))
     if not sync:
         return out, count
-    return out[: int(count.item())]
+    k = int(count.item())
+    if k < 0:
+        raise RuntimeError("mp_set_op: a tile's wait for the tiles before it gave up")
+    return out[:k]
 
 
 def merge_split(A: torch.Tensor, B: torch.Tensor, a_split: torch.Tensor, tile: int = 4096,

@@ -278,10 +278,6 @@ mp_status mp_set_op(int32_t op, mp_dtype kt, const void *A, int64_t na, const vo
       overlaps(rc, rb))
     return fail(MP_ERR_OVERLAP, "%s: S, count, workspace and the inputs must not overlap", fn);
   hipStream_t s = (hipStream_t)stream;
-  if (na + nb == 0) {
-    const hipError_t e = hipMemsetAsync(count, 0, sizeof(int64_t), s);
-    return e == hipSuccess ? MP_OK : hip_fail(e, "mp_set_op");
-  }
   hipError_t e = hipSuccess;
   dispatch_key(kt, [&](auto k) {
     using K = decltype(k);

@@ -22,9 +22,12 @@
 // run start before the window, and wave 0 finds that start in global memory
 // once per tile.  Ranks then advance along the lane's serial merge.
 //
-// Two launches of the same tile kernel: the first counts each tile's kept
-// keys, a one-workgroup scan turns the counts into output offsets (and the
-// total), the second writes the kept keys, compacted through LDS.
+// One pass: each tile's kept keys are compacted through LDS and written at
+// the tile's output offset, found by a decoupled look-back over the tiles
+// before it.  Workgroups take tiles in the order they start (a ticket
+// counter), so every tile a workgroup waits on belongs to a workgroup that
+// is already running; each tile publishes its own count before it waits,
+// so every wait ends, and a bound on the polls backs that up.
 #include <type_traits>
 
 #include "mp_device.h"
@@ -65,20 +68,45 @@ __device__ int64_t wave_first_true(int64_t lo, int64_t hi, P pred) {
   return lo;
 }
 
+// Tile status words of the look-back: 0 = nothing published yet, else a
+// flag in the top two bits and a count below.
+constexpr unsigned long long kSetAggregate = 1ull << 62;  // this tile's own count
+constexpr unsigned long long kSetInclusive = 2ull << 62;  // count of all tiles up to it
+constexpr unsigned long long kSetValue = (1ull << 62) - 1;
+constexpr unsigned kSetMaxPolls = 1u << 22;  // far beyond any real wait
+
+// Start of the run of keys equal to X[p] (p > 0), by the 64 lanes of the
+// calling wavefront: one round over the 64 keys before p, then, for a
+// longer run, the 64-way search over everything before them.
+template <typename K>
+__device__ int64_t run_start(const K *X, int64_t p) {
+  const int lane = threadIdx.x & 63;
+  const K v = X[p];
+  const int64_t q = p - 1 - lane;
+  const uint64_t smaller = __ballot(q < 0 || X[q] < v);
+  if (smaller) return p - (__ffsll((long long)smaller) - 1);  // lane f: X[p-1-f] < v
+  return wave_first_true(0, p - 64, [&](int64_t i) { return !(X[i] < v); });
+}
+
 // OP: 0 intersection, 1 union, 2 difference, 3 symmetric difference.
-// EMIT = false: counts[tile] = keys kept; true: writes them to S at
-// offsets[tile].
-template <typename K, int OP, bool EMIT>
+// status: n_tiles zeroed words; ticket: a zeroed counter; *count: zeroed,
+// receives the output length (-1 if a wait ever gave up, which a correct
+// launch never does; the output is then wrong but every write stays inside
+// the first na + nb slots of S).
+template <typename K, int OP>
 __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     const K *__restrict__ A, int64_t na, const K *__restrict__ B, int64_t nb,
-    const int64_t *__restrict__ a_split, int64_t *__restrict__ counts,
-    const int64_t *__restrict__ offsets, K *__restrict__ S) {
+    const int64_t *__restrict__ a_split, unsigned long long *__restrict__ status,
+    unsigned long long *__restrict__ ticket, int64_t n_tiles, int64_t *__restrict__ count,
+    K *__restrict__ S) {
   constexpr int NT = kSetNT, VT = kSetVT, T = kSetT;
   __shared__ K keys[T + VT + 1];
   __shared__ int s_cnt[NT / 64];
-  __shared__ int64_t s_lb[2];
+  __shared__ int64_t s_lb[2], s_tile, s_excl;
   const int tid = threadIdx.x;
-  const int64_t tile = blockIdx.x;
+  if (tid == 0) s_tile = (int64_t)atomicAdd(ticket, 1ull);
+  __syncthreads();
+  const int64_t tile = s_tile;
   const int64_t N = na + nb;
   const int64_t d0 = tile * T;
   const int64_t d1 = d0 + T < N ? d0 + T : N;
@@ -100,16 +128,8 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
   // when the run reaches back past the window)
   if (tid < 64) {
     int64_t lbA = a0, lbB = b0;
-    if (wa > 0 && a0 > 0) {
-      const K v = A[a0];
-      if (key_eq(A[a0 - 1], v))
-        lbA = wave_first_true(0, a0, [&](int64_t i) { return !(A[i] < v); });
-    }
-    if (wb > 0 && b0 > 0) {
-      const K v = B[b0];
-      if (key_eq(B[b0 - 1], v))
-        lbB = wave_first_true(0, b0, [&](int64_t i) { return !(B[i] < v); });
-    }
+    if (wa > 0 && a0 > 0) lbA = run_start(A, a0);
+    if (wb > 0 && b0 > 0) lbB = run_start(B, b0);
     if (tid == 0) {
       s_lb[0] = lbA;
       s_lb[1] = lbB;
@@ -128,23 +148,32 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
   // ranks of the first A and B copies this lane takes
   int64_t kA = 0, kB = 0;
   K lastA{}, lastB{};
+  // (a search only when the key before it in the window is equal)
   if (ai < wa) {
     lastA = keys[ai];
-    int l = 0, h = ai;  // first position in [0, ai] holding lastA
-    while (l < h) {
-      const int m = (l + h) >> 1;
-      if (keys[m] < lastA) l = m + 1; else h = m;
+    if (ai > 0 && key_eq(keys[ai - 1], lastA)) {
+      int l = 0, h = ai - 1;  // first position in [0, ai - 1] holding lastA
+      while (l < h) {
+        const int m = (l + h) >> 1;
+        if (keys[m] < lastA) l = m + 1; else h = m;
+      }
+      kA = (a0 + ai) - (l > 0 ? a0 + l : s_lb[0]);
+    } else {
+      kA = ai > 0 ? 0 : (a0 + ai) - s_lb[0];
     }
-    kA = (a0 + ai) - (l > 0 ? a0 + l : s_lb[0]);
   }
   if (bi < n) {
     lastB = keys[bi];
-    int l = wa, h = bi;
-    while (l < h) {
-      const int m = (l + h) >> 1;
-      if (keys[m] < lastB) l = m + 1; else h = m;
+    if (bi > wa && key_eq(keys[bi - 1], lastB)) {
+      int l = wa, h = bi - 1;
+      while (l < h) {
+        const int m = (l + h) >> 1;
+        if (keys[m] < lastB) l = m + 1; else h = m;
+      }
+      kB = (b0 + (bi - wa)) - (l > wa ? b0 + (l - wa) : s_lb[1]);
+    } else {
+      kB = bi > wa ? 0 : (b0 + (bi - wa)) - s_lb[1];
     }
-    kB = (b0 + (bi - wa)) - (l > wa ? b0 + (l - wa) : s_lb[1]);
   }
 
   K out[VT];
@@ -204,49 +233,70 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     incl += w < wave ? t : 0;
     total += t;
   }
-  if constexpr (!EMIT) {
-    if (tid == 0) counts[tile] = total;
-  } else {
-    // compact through LDS (the windows are no longer read), then store
-    int pos = incl - c;
+  // output offset: publish this tile's count, then add up the tiles before
+  // it, wave 0 reading 64 of them per round (nearest first) back to the
+  // nearest one that has published its inclusive count
+  if (tid < 64) {
+    int64_t excl = 0;
+    bool gave_up = false;
+    if (tile == 0) {
+      if (tid == 0) atomicExch(&status[0], kSetInclusive | (unsigned long long)total);
+    } else {
+      if (tid == 0) atomicExch(&status[tile], kSetAggregate | (unsigned long long)total);
+      int64_t j_hi = tile - 1;
+      unsigned polls = 0;
+      while (true) {
+        const int64_t j = j_hi - tid;
+        // before tile 0: an inclusive count of 0
+        const unsigned long long v = j >= 0 ? atomicAdd(&status[j], 0ull) : kSetInclusive;
+        const uint64_t inc = __ballot((v & kSetInclusive) != 0);
+        const uint64_t empty = __ballot(v == 0);
+        const int f = inc ? __ffsll((long long)inc) - 1 : 64;  // nearest inclusive lane
+        const uint64_t upto = f >= 63 ? ~0ull : ((2ull << f) - 1);  // lanes 0..f
+        if (empty & upto) {
+          // a tile in range has not published yet: read the window again
+          if (++polls > kSetMaxPolls) {
+            gave_up = true;  // an offset too small keeps the writes in bounds
+            break;
+          }
+          continue;
+        }
+        unsigned long long x = tid <= f ? (v & kSetValue) : 0ull;
 #pragma unroll
-    for (int s = 0; s < VT; ++s)
-      if ((keep >> s) & 1u) keys[pos++] = out[s];
-    __syncthreads();
-    const int64_t base = offsets[tile];
-    for (int i = tid; i < total; i += NT) S[base + i] = keys[i];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        excl += (int64_t)x;
+        if (f < 64) break;
+        j_hi -= 64;
+      }
+      if (tid == 0) atomicExch(&status[tile], kSetInclusive | (unsigned long long)(excl + total));
+    }
+    if (tid == 0) {
+      s_excl = excl;
+      if (gave_up) atomicExch((unsigned long long *)count, ~0ull);
+      else if (tile == n_tiles - 1)
+        atomicCAS((unsigned long long *)count, 0ull, (unsigned long long)(excl + total));
+    }
   }
+  // compact through LDS (the windows are no longer read), then store
+  int pos = incl - c;
+#pragma unroll
+  for (int s = 0; s < VT; ++s)
+    if ((keep >> s) & 1u) keys[pos++] = out[s];
+  __syncthreads();
+  const int64_t base = s_excl;
+  for (int i = tid; i < total; i += NT) S[base + i] = keys[i];
 }
 
-// Exclusive scan of n counts into offsets[0..n] (offsets[n] = total, also
-// written to *total): one workgroup of 1024 lanes, each summing a contiguous
-// share, then a scan of the shares.
-__global__ __launch_bounds__(1024) void setop_scan_kernel(const int64_t *__restrict__ counts,
-                                                          int64_t n, int64_t *__restrict__ offsets,
-                                                          int64_t *__restrict__ total) {
-  __shared__ int64_t s[1024];
-  const int tid = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t lo = tid * per < n ? tid * per : n;
-  const int64_t hi = lo + per < n ? lo + per : n;
-  int64_t sum = 0;
-  for (int64_t i = lo; i < hi; ++i) sum += counts[i];
-  s[tid] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int64_t x = tid >= o ? s[tid - o] : 0;
-    __syncthreads();
-    s[tid] += x;
-    __syncthreads();
-  }
-  int64_t run = s[tid] - sum;
-  for (int64_t i = lo; i < hi; ++i) {
-    offsets[i] = run;
-    run += counts[i];
-  }
-  if (tid == 1023) {
-    offsets[n] = s[1023];
-    *total = s[1023];
+// Zero the look-back state: tile status words, the ticket counter and the
+// output count.
+__global__ void setop_init_kernel(unsigned long long *__restrict__ status, int64_t n_tiles,
+                                  unsigned long long *__restrict__ ticket,
+                                  int64_t *__restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_tiles) status[i] = 0;
+  if (i == 0) {
+    *ticket = 0;
+    *count = 0;
   }
 }
 
@@ -256,17 +306,18 @@ template <typename K>
 hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb, K *S,
                          int64_t *count, int64_t *ws, hipStream_t s) {
   const int64_t n_tiles = setop_tiles(na + nb);
-  int64_t *splits = ws, *counts = ws + (n_tiles + 1), *offsets = counts + (n_tiles + 1);
+  int64_t *splits = ws;
+  unsigned long long *status = (unsigned long long *)(ws + (n_tiles + 1));
+  unsigned long long *ticket = status + n_tiles;
+  hipLaunchKernelGGL(setop_init_kernel, dim3((unsigned)((n_tiles + 256) / 256)), dim3(256), 0, s,
+                     status, n_tiles, ticket, count);
+  if (n_tiles == 0) return hipGetLastError();  // empty inputs: the count is 0
   hipError_t e = launch_partition<K>(A, na, B, nb, nullptr, kSetT, n_tiles + 1, splits, s);
   if (e != hipSuccess) return e;
   auto run = [&](auto opc) {
     constexpr int OP = decltype(opc)::value;
-    hipLaunchKernelGGL((setop_tile_kernel<K, OP, false>), dim3((unsigned)n_tiles), dim3(kSetNT),
-                       0, s, A, na, B, nb, splits, counts, offsets, S);
-    hipLaunchKernelGGL(setop_scan_kernel, dim3(1), dim3(1024), 0, s, counts, n_tiles, offsets,
-                       count);
-    hipLaunchKernelGGL((setop_tile_kernel<K, OP, true>), dim3((unsigned)n_tiles), dim3(kSetNT),
-                       0, s, A, na, B, nb, splits, counts, offsets, S);
+    hipLaunchKernelGGL((setop_tile_kernel<K, OP>), dim3((unsigned)n_tiles), dim3(kSetNT), 0, s, A,
+                       na, B, nb, splits, status, ticket, n_tiles, count, S);
   };
   switch (op) {
     case 0: run(std::integral_constant<int, 0>()); break;
