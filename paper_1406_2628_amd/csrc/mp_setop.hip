@@ -181,36 +181,38 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
 #pragma unroll
   for (int s = 0; s < VT; ++s) {
     if (s < steps) {
+      // one path for both sides (no divergence between A and B steps)
       const bool take_b = (bi < n) && (ai >= wa || keys[bi] < keys[ai]);
-      if (!take_b) {
-        const K v = keys[ai];
-        if (!key_eq(v, lastA)) {
-          kA = 0;
-          lastA = v;
-        }
-        // matched: B[lb_B + k] == v, lb_B = the path's b here
-        const int64_t jb = b0 + (bi - wa) + kA;
-        bool m = false;
-        if (jb < nb) m = key_eq(jb - b0 < wb ? keys[wa + (int)(jb - b0)] : B[jb], v);
-        out[s] = v;
-        if (OP == 1 || (OP == 0 ? m : !m)) keep |= 1u << s;
-        ++kA;
-        ++ai;
+      const K v = take_b ? keys[bi] : keys[ai];
+      // rank of this copy within its run on its own side
+      if (take_b) {
+        kB = key_eq(v, lastB) ? kB : 0;
+        lastB = v;
       } else {
-        const K v = keys[bi];
-        if (!key_eq(v, lastB)) {
-          kB = 0;
-          lastB = v;
-        }
-        // matched: A[ub_A - 1 - k] == v, ub_A = the path's a here
-        const int64_t ia = a0 + ai - 1 - kB;
-        bool m = false;
-        if (ia >= 0) m = key_eq(ia >= a0 ? keys[(int)(ia - a0)] : A[ia], v);
-        out[s] = v;
-        if ((OP == 1 || OP == 3) && !m) keep |= 1u << s;
-        ++kB;
-        ++bi;
+        kA = key_eq(v, lastA) ? kA : 0;
+        lastA = v;
       }
+      const int64_t k = take_b ? kB : kA;
+      // partner: an A copy's is B[b + k] (b = the path's b, where the run
+      // starts in B); a B copy's is A[a - 1 - k] (a = the path's a, where
+      // the run ends in A)
+      const int64_t q = take_b ? a0 + ai - 1 - k : b0 + (bi - wa) + k;
+      const bool in_range = take_b ? q >= 0 : q < nb;
+      const bool in_win = take_b ? q >= a0 : q - b0 < wb;
+      bool m = false;
+      if (in_range) {
+        const K w = in_win ? keys[take_b ? (int)(q - a0) : wa + (int)(q - b0)]
+                           : (take_b ? A[q] : B[q]);
+        m = key_eq(w, v);
+      }
+      out[s] = v;
+      const bool keep_a = OP == 1 || (OP == 0 ? m : !m);
+      const bool keep_b = (OP == 1 || OP == 3) && !m;
+      if (take_b ? keep_b : keep_a) keep |= 1u << s;
+      kA += take_b ? 0 : 1;
+      kB += take_b ? 1 : 0;
+      ai += take_b ? 0 : 1;
+      bi += take_b ? 1 : 0;
     }
   }
 
