@@ -5,6 +5,10 @@ on the device against closed forms that hold at any size.
   Every value appears twice in each input, and ties take A first, so the
   merge holds each value four times: S[p] = floor(p / 4) over 3 * 2^31
   outputs, and the split on diagonal d = 4v + r is a = 2v + min(r, 2).
+* Set operations: A[i] = floor(i / 2), B[j] = floor(j / 3), |A| = |B| =
+  3 * 2^30: values below 2^30 appear twice in A and three times in B, the
+  values from 2^30 to 1.5 * 2^30 twice in A only, which fixes every output
+  (up to 2^32 keys) in closed form.
 * Sort: keys k_i = (i * 0x9E3779B1) mod 2^32 for i < 2^31 + 12345 are
   distinct (multiplying by an odd constant is a bijection modulo 2^32), so
   with values v_i = i the sorted keys must increase strictly and every value
@@ -74,6 +78,48 @@ def test_merge_and_partition_past_2p32_outputs(mp):
     got = mp.partition(A, B, torch.from_numpy(d).cuda()).cpu().numpy()
     want = 2 * (d // 4) + np.minimum(d % 4, 2)
     assert np.array_equal(got, want)
+
+
+def _third_index(n):
+    """uint32 tensor t[i] = floor(i / 3), built in chunks."""
+    import torch
+    t = torch.empty(n, dtype=torch.uint32, device="cuda")
+    for s in range(0, n, CHUNK):
+        e = min(n, s + CHUNK)
+        t[s:e] = _u32_from(torch.arange(s, e, dtype=torch.int64, device="cuda") // 3)
+    return t
+
+
+def test_set_ops_past_2p32_outputs(mp):
+    import torch
+    _need(56)
+    na = nb = 3 << 30
+    A = _half_index(na)
+    B = _third_index(nb)
+    H = 1 << 30
+    out = torch.empty(na + nb, dtype=torch.uint32, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    ws = torch.empty(mp.lib().mp_set_op_workspace_bytes(na, nb), dtype=torch.uint8, device="cuda")
+
+    def union_ref(p):
+        return torch.where(p < 3 * H, p // 3, H + (p - 3 * H) // 2)
+
+    def symdiff_ref(p):
+        return torch.where(p < H, p, H + (p - H) // 2)
+
+    expect = {"intersection": (1 << 31, lambda p: p >> 1),
+              "union": (1 << 32, union_ref),
+              "difference": (H, lambda p: H + (p >> 1)),
+              "symmetric_difference": (1 << 31, symdiff_ref)}
+    for op, (length, ref) in expect.items():
+        mp.set_op(op, A, B, out=out, count=cnt, ws=ws, sync=False)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == length, op
+        for s in range(0, length, CHUNK):
+            e = min(length, s + CHUNK)
+            got = out[s:e].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+            want = ref(torch.arange(s, e, dtype=torch.int64, device="cuda"))
+            assert torch.equal(got, want), (op, s)
 
 
 def test_sort_kv_past_2p31_keys(mp):
