@@ -85,7 +85,8 @@ hipError_t launch_merge_checksum(StreamCfg cfg, const K *A, int64_t na, const K 
 
 // Multiset operation (0 intersection, 1 union, 2 difference, 3 symmetric
 // difference) of sorted A and B into S; *count (device) receives the output
-// length.  ws: 3 * (setop_tiles(na + nb) + 1) int64 of device workspace.
+// length.  ws: 3 * (setop_tiles(na + nb) + 1) int64 of device workspace
+// (setop_tiles bounds the tile count of every key type).
 int64_t setop_tiles(int64_t n);
 template <typename K>
 hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb, K *S,

@@ -35,7 +35,12 @@
 
 namespace mp {
 
-constexpr int kSetNT = 256, kSetVT = 16, kSetT = kSetNT * kSetVT;
+// 512 lanes per tile, each taking 24 outputs for 4-byte keys and 12 for
+// 8-byte keys (48 KiB of LDS either way)
+constexpr int kSetNT = 512;
+template <typename K>
+constexpr int kSetVT = sizeof(K) == 4 ? 24 : 12;
+constexpr int kSetTMin = kSetNT * 12;  // the smaller tile, for workspace bounds
 
 template <typename K>
 __device__ __forceinline__ bool key_eq(K x, K y) {
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     const int64_t *__restrict__ a_split, unsigned long long *__restrict__ status,
     unsigned long long *__restrict__ ticket, int64_t n_tiles, int64_t *__restrict__ count,
     K *__restrict__ S) {
-  constexpr int NT = kSetNT, VT = kSetVT, T = kSetT;
+  constexpr int NT = kSetNT, VT = kSetVT<K>, T = NT * VT;
   __shared__ K keys[T + VT + 1];
   __shared__ int s_cnt[NT / 64];
   __shared__ int64_t s_lb[2], s_tile, s_excl;
@@ -122,8 +127,15 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
   const int64_t wa_hi = na - a0 < (int64_t)n ? na - a0 : (int64_t)n;
   wa64 = wa64 < wa_lo ? wa_lo : (wa64 > wa_hi ? wa_hi : wa64);
   const int wa = (int)wa64, wb = n - wa;
-  for (int i = tid; i < wa; i += NT) keys[i] = A[a0 + i];
-  for (int i = tid; i < wb; i += NT) keys[wa + i] = B[b0 + i];
+  // the pair back to back in LDS: each lane issues all its VT loads into
+  // registers before the first LDS write, so they are in flight together
+  K stage[VT];
+#pragma unroll
+  for (int s = 0; s < VT; ++s) {
+    const int i = tid + s * NT;
+    const K *p = i < wa ? A + (a0 + i) : B + (b0 + (i - wa));
+    if (i < n) stage[s] = *p;
+  }
   // run starts of the window's first A and first B value (global search only
   // when the run reaches back past the window)
   if (tid < 64) {
@@ -134,6 +146,11 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
       s_lb[0] = lbA;
       s_lb[1] = lbB;
     }
+  }
+#pragma unroll
+  for (int s = 0; s < VT; ++s) {
+    const int i = tid + s * NT;
+    if (i < n) keys[i] = stage[s];
   }
   __syncthreads();
 
@@ -302,19 +319,20 @@ __global__ void setop_init_kernel(unsigned long long *__restrict__ status, int64
   }
 }
 
-int64_t setop_tiles(int64_t n) { return (n + kSetT - 1) / kSetT; }
+int64_t setop_tiles(int64_t n) { return (n + kSetTMin - 1) / kSetTMin; }
 
 template <typename K>
 hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb, K *S,
                          int64_t *count, int64_t *ws, hipStream_t s) {
-  const int64_t n_tiles = setop_tiles(na + nb);
+  constexpr int T = kSetNT * kSetVT<K>;
+  const int64_t n_tiles = (na + nb + T - 1) / T;  // at most setop_tiles(na + nb)
   int64_t *splits = ws;
   unsigned long long *status = (unsigned long long *)(ws + (n_tiles + 1));
   unsigned long long *ticket = status + n_tiles;
   hipLaunchKernelGGL(setop_init_kernel, dim3((unsigned)((n_tiles + 256) / 256)), dim3(256), 0, s,
                      status, n_tiles, ticket, count);
   if (n_tiles == 0) return hipGetLastError();  // empty inputs: the count is 0
-  hipError_t e = launch_partition<K>(A, na, B, nb, nullptr, kSetT, n_tiles + 1, splits, s);
+  hipError_t e = launch_partition<K>(A, na, B, nb, nullptr, T, n_tiles + 1, splits, s);
   if (e != hipSuccess) return e;
   auto run = [&](auto opc) {
     constexpr int OP = decltype(opc)::value;

@@ -75,7 +75,20 @@ def test_set_op_runs_across_many_tiles(mp, orc, op):
     """Runs of equal keys longer than a tile, starting anywhere: the global
     run-start search of each tile."""
     g = np.random.default_rng(86)
-    vals = np.sort(g.choice(1 << 30, 40, replace=False)).astype(np.uint32)
+    vals = np.sort(g.choice(1 << 30, 20, replace=False)).astype(np.uint32)
     A = np.sort(g.choice(vals, 400_000)).astype(np.uint32)
     B = np.sort(g.choice(vals, 300_001)).astype(np.uint32)
+    _check(mp, orc, op, A, B)
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dt", [gen.U32, gen.U64])
+def test_set_op_lookback_over_many_tiles(mp, orc, op, dt):
+    """Hundreds of tiles, so each output offset adds up more than one round
+    of 64 predecessors; the sizes leave a ragged last tile."""
+    _check(mp, orc, op, *gen.uniform_pair(1_500_007, 1_300_001, 87, dt))
+    g = np.random.default_rng(88)
+    npd = gen.NP_DTYPE[dt]
+    A = np.sort(g.integers(0, 2_000_000, 1_500_007)).astype(npd)
+    B = np.sort(g.integers(0, 2_000_000, 1_300_001)).astype(npd)
     _check(mp, orc, op, A, B)
