@@ -124,14 +124,28 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(
   wa64 = wa64 < wa_lo ? wa_lo : (wa64 > wa_hi ? wa_hi : wa64);
   const int wa = (int)wa64, wb = n - wa;
 
-  // Stage the pair (A[a0, a1), B[b0, b1)) back to back in LDS.
-  for (int i = tid; i < n; i += NT) {
-    if (i < wa) {
-      keys[i] = A[a0 + i];
-      if constexpr (KV) vals[i] = Av[a0 + i];
-    } else {
-      keys[i] = B[b0 + i - wa];
-      if constexpr (KV) vals[i] = Bv[b0 + i - wa];
+  // Stage the pair (A[a0, a1), B[b0, b1)) back to back in LDS.  Each lane
+  // issues all its loads into registers before its first LDS write, so they
+  // are in flight together.
+  {
+    K rk[VT];
+    uint32_t rv[KV ? VT : 1];
+#pragma unroll
+    for (int s = 0; s < VT; ++s) {
+      const int i = tid + s * NT;
+      const int64_t g = i < wa ? a0 + i : b0 + (i - wa);
+      if (i < n) {
+        rk[s] = (i < wa ? A : B)[g];
+        if constexpr (KV) rv[s] = (i < wa ? Av : Bv)[g];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < VT; ++s) {
+      const int i = tid + s * NT;
+      if (i < n) {
+        keys[i] = rk[s];
+        if constexpr (KV) vals[i] = rv[s];
+      }
     }
   }
   __syncthreads();
