@@ -62,6 +62,26 @@ def time_steps(fn, steps, warmup):
     return start.elapsed_time(stop) / steps
 
 
+def event_times(fn, steps, warmup):
+    """Per-call times (ms) of `steps` calls after `warmup` calls, each call
+    bracketed by its own pair of events on the current stream: mean, median
+    and min."""
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        fn()
+    sync()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for s, e in evs:
+        s.record()
+        fn()
+        e.record()
+    sync()
+    ts = np.array([s.elapsed_time(e) for s, e in evs])
+    return {"mean": float(ts.mean()), "median": float(np.median(ts)), "min": float(ts.min())}
+
+
 def time_each(fn, setup, reps, warmup=1):
     """Median ms of fn() over reps, each preceded by an untimed setup()."""
     import numpy as np
@@ -212,6 +232,37 @@ def leg_headline(args, out):
                        "read_frac": round(n_out * 4 / (nw_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                        "store_over_no_store": round(ms / nw_ms, 3),
                        "checksum_matches_oracle": ck_got == ck_want}
+
+
+def bw_sweep(args):
+    """Bandwidth references (mp_bw_probe): copy, read-only and write-only
+    passes moving 4.3 GB and 8.6 GB in total, over a sweep of loads or stores
+    in flight per lane and workgroups per compute unit.  One JSON line per
+    point: median and min of event-timed launches."""
+    import torch
+
+    import paper_1406_2628_amd as mp
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for moved in (1 << 32, 1 << 33):
+        for kind in ("copy", "read", "write"):
+            n = moved // 2 if kind == "copy" else moved
+            src = None if kind == "write" else torch.ones(n // 4, dtype=torch.int32, device="cuda")
+            for per_cu in (4, 8, 16, 32, 64):
+                grid = per_cu * cus
+                dst = (torch.empty(grid * 64, dtype=torch.int32, device="cuda") if kind == "read"
+                       else torch.empty(n // 4, dtype=torch.int32, device="cuda"))
+                for unroll in (1, 2, 4, 8, 16):
+                    ts = event_times(lambda: mp.bw_probe(kind, src, dst, n, unroll, grid),
+                                     args.steps, args.warmup)
+                    print(json.dumps({"probe": kind, "bytes_moved": moved, "per_cu": per_cu,
+                                      "grid": grid, "unroll": unroll,
+                                      "median_ms": round(ts["median"], 4),
+                                      "min_ms": round(ts["min"], 4),
+                                      "GBs_median": round(moved / ts["median"] / 1e6, 1),
+                                      "GBs_best": round(moved / ts["min"] / 1e6, 1)}), flush=True)
+                del dst
+            del src
+            torch.cuda.empty_cache()
 
 
 # ---------------------------------------------------------------------------
@@ -475,6 +526,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time only the reference copy of the headline's byte count")
+    ap.add_argument("--bw-sweep", action="store_true",
+                    help="only the bandwidth references: copy / read / write sweeps")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -486,6 +539,9 @@ def main():
 
     import torch
     torch.cuda.set_device(0)
+    if args.bw_sweep:
+        bw_sweep(args)
+        return
     legs = [x for x in args.legs.split(",") if x]
     out = {}
     leg_headline(args, out)

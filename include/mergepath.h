@@ -123,6 +123,8 @@ mp_status mp_merge(mp_dtype kt, const void *A, int64_t na, const void *B,
  *          library's set algorithms).
  *   S      room for na keys (intersection, difference) or na + nb keys
  *          (union, symmetric difference); the first *count are written.
+ *          No store ever lands past that room, unsorted inputs included
+ *          (their count is then clamped to it).
  *   count  one int64 in device memory (8-byte aligned): the output length,
  *          written when the work runs.  One pass: each tile finds its output
  *          offset by looking back over the tiles before it (tiles are taken
@@ -328,8 +330,10 @@ mp_status mp_lp_load(mp_lp *h, const char *path);
  *   cfg   NULL restores the built-in choice (persistent; merge nt 192,
  *         vt 24, but nt 256, vt 12 for 8-byte keys with values; batched
  *         and sort nt 256, vt 16); otherwise
- *         mode: 1 = per-tile (one grid split search per output tile, then
- *                   one workgroup per tile; Algorithm 1 with p = tiles),
+ *         mode: 1 = per-tile (one workgroup per output tile, which finds
+ *                   the splits on its tile's two diagonals itself in global
+ *                   memory; Algorithm 1 with p = tiles; no memory beyond
+ *                   the inputs and outputs),
  *               2 = persistent (each workgroup finds one split and walks a
  *                   contiguous run of tiles, finding each next split in
  *                   on-chip memory; Algorithm 3, Theorem 17)
@@ -405,11 +409,26 @@ int64_t mp_graph_count(void);
  * loads and nontemporal stores the merge kernels use.  A measurement
  * reference for achievable HBM bandwidth and for calibrating hardware
  * traffic counters; not part of the merge method.
- *   unroll  16-byte loads in flight per lane: 1, 2, 4 or 8 (0 = 8)
+ *   unroll  16-byte loads in flight per lane: 1, 2, 4, 8 (0 = 8) or 16
  *   grid    workgroups of 256 lanes (0 = 32 per compute unit)
  */
 mp_status mp_copy(const void *src, void *dst, int64_t n_bytes, int32_t unroll,
                   int32_t grid, void *stream);
+
+/*
+ * mp_bw_probe -- bandwidth references for the roofline: the copy above
+ * (kind 0), the same loads alone (kind 1: src is read, and each wavefront
+ * stores the XOR of what it read to dst, which must hold grid * 4 16-byte
+ * words; grid 0 means 32 per compute unit, the count used for the sink)
+ * and the same stores alone (kind 2: dst receives n_bytes of a fixed
+ * pattern, src is unused and may be NULL).  Not part of the merge method.
+ *   n_bytes  multiple of 16; pointers 16-byte aligned; unroll 1, 2, 4, 8
+ *            (0 = 8) or 16 loads or stores in flight per lane.
+ * MP_ERR_INVALID_ARG for a bad kind, size or pointer, MP_ERR_OVERLAP when
+ * src and dst (as used) overlap, MP_ERR_UNSUPPORTED for another unroll.
+ */
+mp_status mp_bw_probe(int32_t kind, const void *src, void *dst, int64_t n_bytes,
+                      int32_t unroll, int32_t grid, void *stream);
 
 /*
  * Kernel timing (profiling aid, off by default).  While enabled, every kernel

@@ -69,6 +69,7 @@ def _declare(L):
         "mp_autotune_batched": ([i32, p, p, p, p, i64, i64, i64, p, i32, p, p], i32),
         "mp_autotune_sort": ([i32, i32, p, p, p, p, i64, p, sz, i32, p, p], i32),
         "mp_copy": ([p, p, i64, i32, i32, p], i32),
+        "mp_bw_probe": ([i32, p, p, i64, i32, i32, p], i32),
         "mp_timing_enable": ([i32], i32),
         "mp_timing_reset": ([], i32),
         "mp_timing_query": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -141,6 +142,18 @@ def copy(src: torch.Tensor, dst: torch.Tensor, unroll: int = 0, grid: int = 0):
     """Reference streaming copy of src's bytes into dst (bandwidth probe)."""
     n = src.numel() * src.element_size()
     _check(lib().mp_copy(_ptr(src), _ptr(dst), n, unroll, grid, _stream(src.device)))
+
+
+BW_KINDS = {"copy": 0, "read": 1, "write": 2}
+
+
+def bw_probe(kind: str, src: torch.Tensor | None, dst: torch.Tensor, n_bytes: int,
+             unroll: int = 0, grid: int = 0):
+    """Bandwidth reference: copy, read-only or write-only pass over n_bytes
+    (for 'read', dst is the small per-wavefront sink)."""
+    dev_ = dst.device
+    _check(lib().mp_bw_probe(BW_KINDS[kind], _ptr(src), _ptr(dst), n_bytes, unroll, grid,
+                             _stream(dev_)))
 
 
 def timing_enable(on: bool = True):

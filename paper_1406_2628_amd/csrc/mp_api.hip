@@ -101,35 +101,6 @@ int device_cu_count() {
   return cache[dev];
 }
 
-void *device_scratch(size_t bytes, hipError_t *err) {
-  struct Slot {
-    void *p = nullptr;
-    size_t size = 0;
-  };
-  static std::mutex mu;
-  static std::vector<Slot> slots;
-  int dev = 0;
-  *err = hipGetDevice(&dev);
-  if (*err != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lock(mu);
-  if ((int)slots.size() <= dev) slots.resize(dev + 1);
-  Slot &s = slots[dev];
-  if (s.size < bytes) {
-    if (s.p) {
-      *err = hipDeviceSynchronize();
-      if (*err != hipSuccess) return nullptr;
-      (void)hipFree(s.p);
-      s.p = nullptr;
-      s.size = 0;
-    }
-    *err = hipMalloc(&s.p, bytes);
-    if (*err != hipSuccess) return nullptr;
-    s.size = bytes;
-  }
-  *err = hipSuccess;
-  return s.p;
-}
-
 }  // namespace mp
 
 using namespace mp;
@@ -207,23 +178,14 @@ static mp_status merge_common(const char *fn, mp_dtype kt, mp_dtype vt,
   }
   hipError_t e = hipSuccess;
   if (cfg.mode == 1) {
+    // one workgroup per tile, each finding its own two splits
     const TileCfg tc{cfg.nt, cfg.vt};
-    const int64_t T = (int64_t)tc.nt * tc.vt;
-    const int64_t n_tiles = (n + T - 1) / T;
-    int64_t *splits = (int64_t *)device_scratch((size_t)(n_tiles + 1) * 8, &e);
-    if (!splits) return hip_fail(e, "workspace allocation");
     dispatch_key(kt, [&](auto k) {
       using K = decltype(k);
-      {
-        KernelTimer timer("tile_partition", s);
-        e = launch_partition<K>((const K *)Ak, na, (const K *)Bk, nb, nullptr, T,
-                                n_tiles + 1, splits, s);
-      }
-      if (e != hipSuccess) return;
       KernelTimer timer("merge_tiles", s);
       e = launch_merge_tiles<K>(tc, (const K *)Ak, (const uint32_t *)Av, na,
                                 (const K *)Bk, (const uint32_t *)Bv, nb, (K *)Sk,
-                                kv ? (uint32_t *)Sv : nullptr, splits, s);
+                                kv ? (uint32_t *)Sv : nullptr, nullptr, s);
     });
   } else {
     const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
@@ -282,7 +244,8 @@ mp_status mp_set_op(int32_t op, mp_dtype kt, const void *A, int64_t na, const vo
   dispatch_key(kt, [&](auto k) {
     using K = decltype(k);
     KernelTimer timer("set_op", s);
-    e = launch_set_op<K>(op, (const K *)A, na, (const K *)B, nb, (K *)S, count, (int64_t *)ws, s);
+    e = launch_set_op<K>(op, (const K *)A, na, (const K *)B, nb, (K *)S, cap, count,
+                         (int64_t *)ws, s);
   });
   return e == hipSuccess ? MP_OK : hip_fail(e, "mp_set_op launch");
 }
@@ -398,6 +361,28 @@ mp_status mp_copy(const void *src, void *dst, int64_t n_bytes, int32_t unroll,
   hipError_t e = launch_copy(src, dst, n_bytes, unroll, grid, (hipStream_t)stream);
   if (e == hipErrorNotSupported) return fail(MP_ERR_UNSUPPORTED, "mp_copy: unroll %d not provided", unroll);
   return e == hipSuccess ? MP_OK : hip_fail(e, "mp_copy launch");
+}
+
+mp_status mp_bw_probe(int32_t kind, const void *src, void *dst, int64_t n_bytes, int32_t unroll,
+                      int32_t grid, void *stream) {
+  const char *fn = "mp_bw_probe";
+  if (kind < 0 || kind > 2) return fail(MP_ERR_INVALID_ARG, "%s: kind must be 0, 1 or 2", fn);
+  if (n_bytes < 0 || n_bytes % 16)
+    return fail(MP_ERR_INVALID_ARG, "%s: n_bytes must be a non-negative multiple of 16", fn);
+  if (grid < 0) return fail(MP_ERR_INVALID_ARG, "%s: negative grid", fn);
+  if (n_bytes == 0) return MP_OK;
+  const int g = grid > 0 ? grid : device_cu_count() * 32;
+  const bool need_src = kind != 2;
+  if ((need_src && (!src || (uintptr_t)src % 16)) || !dst || (uintptr_t)dst % 16)
+    return fail(MP_ERR_INVALID_ARG, "%s: pointers must be non-NULL and 16-byte aligned", fn);
+  // the read probe's sink holds one 16-byte word per wavefront
+  const int64_t dst_bytes = kind == 1 ? (int64_t)g * 4 * 16 : n_bytes;
+  if (need_src && overlaps(span(src, n_bytes, 1), span(dst, dst_bytes, 1)))
+    return fail(MP_ERR_OVERLAP, "%s: ranges overlap", fn);
+  KernelTimer timer("bw_probe", (hipStream_t)stream);
+  hipError_t e = launch_bw_probe(kind, src, dst, n_bytes, unroll, g, (hipStream_t)stream);
+  if (e == hipErrorNotSupported) return fail(MP_ERR_UNSUPPORTED, "%s: unroll %d not provided", fn, unroll);
+  return e == hipSuccess ? MP_OK : hip_fail(e, "mp_bw_probe launch");
 }
 
 size_t mp_merge_batched_workspace_bytes(mp_dtype kt, int64_t n_pairs, int64_t total) {

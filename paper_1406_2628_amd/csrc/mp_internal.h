@@ -53,7 +53,9 @@ hipError_t launch_partition(const K *A, int64_t na, const K *B, int64_t nb,
                             int64_t *a_split, hipStream_t s);
 
 // Per-tile merge of T = nt * vt outputs per workgroup, given the splits of
-// every tile boundary (n_tiles + 1 entries).  Av/Bv/Sv may be null (keys only).
+// every tile boundary (n_tiles + 1 entries), or with a_split == nullptr
+// finding each tile's two splits inside its own workgroup.  Av/Bv/Sv may be
+// null (keys only).
 template <typename K>
 hipError_t launch_merge_tiles(TileCfg cfg, const K *A, const uint32_t *Av,
                               int64_t na, const K *B, const uint32_t *Bv,
@@ -84,13 +86,14 @@ hipError_t launch_merge_checksum(StreamCfg cfg, const K *A, int64_t na, const K 
                                  unsigned long long *checksum, hipStream_t s);
 
 // Multiset operation (0 intersection, 1 union, 2 difference, 3 symmetric
-// difference) of sorted A and B into S; *count (device) receives the output
-// length.  ws: 3 * (setop_tiles(na + nb) + 1) int64 of device workspace
-// (setop_tiles bounds the tile count of every key type).
+// difference) of sorted A and B into S (cap slots; no store beyond them);
+// *count (device) receives the output length.  ws: 3 * (setop_tiles(na + nb)
+// + 1) int64 of device workspace (setop_tiles bounds the tile count of every
+// key type).
 int64_t setop_tiles(int64_t n);
 template <typename K>
 hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb, K *S,
-                         int64_t *count, int64_t *ws, hipStream_t s);
+                         int64_t cap, int64_t *count, int64_t *ws, hipStream_t s);
 
 // Batched merge of CSR-concatenated pairs (persistent, one launch).
 template <typename K>
@@ -117,6 +120,10 @@ hipError_t launch_blocksort(const K *in, const uint32_t *vin, K *out, uint32_t *
 // Plain 16-byte streaming copy (bandwidth reference).
 hipError_t launch_copy(const void *src, void *dst, int64_t n_bytes, int unroll,
                        int grid, hipStream_t s);
+// Bandwidth probes: kind 0 copy, 1 read only (per-wavefront XOR to dst,
+// grid * 4 vectors), 2 write only (to dst).
+hipError_t launch_bw_probe(int kind, const void *src, void *dst, int64_t n_bytes, int unroll,
+                           int grid, hipStream_t s);
 
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
@@ -151,8 +158,5 @@ mp_status set_error(mp_status st, const char *fmt, ...);
 // timing is enabled, nullptr otherwise.
 unsigned long long *stats_device_ptr();
 
-// Per-device scratch buffer owned by the library (grown on demand, kept until
-// the process ends).
-void *device_scratch(size_t bytes, hipError_t *err);
 
 }  // namespace mp

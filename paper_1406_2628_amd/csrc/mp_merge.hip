@@ -92,30 +92,53 @@ hipError_t launch_partition(const K *A, int64_t na, const K *B, int64_t nb,
   return hipGetLastError();
 }
 
-template <typename K, bool KV, int NT, int VT>
+// SEARCH = false: the splits of the tile's two diagonals come from a_split
+// (mp_merge_split).  SEARCH = true: the workgroup finds them itself, wave 0
+// on the start diagonal and wave 1 on the end diagonal at once, each probing
+// 64 points per round (Theorem 14's search with a 65-way cut); this is
+// Algorithm 1 with one processor per tile and needs no memory beyond the
+// inputs and the output.
+template <typename K, bool KV, int NT, int VT, bool SEARCH>
 __global__ __launch_bounds__(NT) void merge_tile_kernel(
     const K *__restrict__ A, const uint32_t *__restrict__ Av, int64_t na,
     const K *__restrict__ B, const uint32_t *__restrict__ Bv, int64_t nb,
     K *__restrict__ S, uint32_t *__restrict__ Sv,
     const int64_t *__restrict__ a_split) {
+  static_assert(!SEARCH || NT >= 128, "the in-kernel searches need two wavefronts");
   constexpr int T = NT * VT;
   // slack of VT + 1 slots: the unguarded serial merge may read up to VT
   // positions past the A window end (outputs discarded)
   __shared__ __attribute__((aligned(16))) K keys[T + VT + 1];
   __shared__ __attribute__((aligned(16))) uint32_t vals[KV ? T : 1];
+  __shared__ int64_t s_a[SEARCH ? 2 : 1];
   const int tid = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t n_all = na + nb;
   const int64_t d0 = tile * T;
   const int64_t d1 = d0 + T < n_all ? d0 + T : n_all;
+  int64_t a0, a1;
+  if constexpr (SEARCH) {
+    if (tid < 128) {
+      const int64_t d = tid < 64 ? d0 : d1;
+      int64_t lo, hi;
+      diag_range<int64_t>(d, na, nb, lo, hi);
+      const int64_t a = group_split_search<64, int64_t>(
+          d, lo, hi, [&](int64_t i) { return A[i]; }, [&](int64_t j) { return B[j]; });
+      if ((tid & 63) == 0) s_a[tid >> 6] = a;
+    }
+    __syncthreads();
+    a0 = s_a[0];
+    a1 = s_a[1];
+  } else {
+    a0 = a_split[tile];
+    a1 = a_split[tile + 1];
+  }
   // The splits may come from the caller (mp_merge_split): a0 is kept on the
   // start diagonal inside the grid and the window width below in its valid
   // range, so every access stays in bounds whatever the split values.  For
   // true splits of sorted inputs both clamps change nothing.
   const int64_t lo0 = d0 > nb ? d0 - nb : 0, hi0 = d0 < na ? d0 : na;
-  int64_t a0 = a_split[tile];
   a0 = a0 < lo0 ? lo0 : (a0 > hi0 ? hi0 : a0);
-  const int64_t a1 = a_split[tile + 1];
   const int64_t b0 = d0 - a0;
   const int n = (int)(d1 - d0);
   int64_t wa64 = a1 - a0;
@@ -210,8 +233,12 @@ static hipError_t launch_tiles_impl(const K *A, const uint32_t *Av, int64_t na,
   constexpr int64_t T = NT * VT;
   const int64_t n_tiles = (na + nb + T - 1) / T;
   if (n_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL((merge_tile_kernel<K, KV, NT, VT>), dim3((unsigned)n_tiles),
-                     dim3(NT), 0, s, A, Av, na, B, Bv, nb, S, Sv, a_split);
+  if (a_split)
+    hipLaunchKernelGGL((merge_tile_kernel<K, KV, NT, VT, false>), dim3((unsigned)n_tiles),
+                       dim3(NT), 0, s, A, Av, na, B, Bv, nb, S, Sv, a_split);
+  else
+    hipLaunchKernelGGL((merge_tile_kernel<K, KV, NT, VT, true>), dim3((unsigned)n_tiles),
+                       dim3(NT), 0, s, A, Av, na, B, Bv, nb, S, Sv, nullptr);
   return hipGetLastError();
 }
 

@@ -96,14 +96,17 @@ __device__ int64_t run_start(const K *X, int64_t p) {
 // OP: 0 intersection, 1 union, 2 difference, 3 symmetric difference.
 // status: n_tiles zeroed words; ticket: a zeroed counter; *count: zeroed,
 // receives the output length (-1 if a wait ever gave up, which a correct
-// launch never does; the output is then wrong but every write stays inside
-// the first na + nb slots of S).
+// launch never does).  cap: the slots of S.  Sorted inputs never keep more
+// than cap keys, but unsorted ones can: their splits need not increase from
+// tile to tile, so the tiles' pairs may overlap and together keep more keys
+// than either input holds.  Every store is therefore bounded by cap, and the
+// count is clamped to it.
 template <typename K, int OP>
 __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     const K *__restrict__ A, int64_t na, const K *__restrict__ B, int64_t nb,
     const int64_t *__restrict__ a_split, unsigned long long *__restrict__ status,
     unsigned long long *__restrict__ ticket, int64_t n_tiles, int64_t *__restrict__ count,
-    K *__restrict__ S) {
+    K *__restrict__ S, int64_t cap) {
   constexpr int NT = kSetNT, VT = kSetVT<K>, T = NT * VT;
   __shared__ K keys[T + VT + 1];
   __shared__ int s_cnt[NT / 64];
@@ -291,9 +294,10 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     }
     if (tid == 0) {
       s_excl = excl;
+      const int64_t end = excl + total < cap ? excl + total : cap;
       if (gave_up) atomicExch((unsigned long long *)count, ~0ull);
       else if (tile == n_tiles - 1)
-        atomicCAS((unsigned long long *)count, 0ull, (unsigned long long)(excl + total));
+        atomicCAS((unsigned long long *)count, 0ull, (unsigned long long)end);
     }
   }
   // compact through LDS (the windows are no longer read), then store
@@ -303,7 +307,9 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     if ((keep >> s) & 1u) keys[pos++] = out[s];
   __syncthreads();
   const int64_t base = s_excl;
-  for (int i = tid; i < total; i += NT) S[base + i] = keys[i];
+  const int64_t room = cap - base;  // slots of S left from this tile's offset
+  const int lim = room < (int64_t)total ? (room > 0 ? (int)room : 0) : total;
+  for (int i = tid; i < lim; i += NT) S[base + i] = keys[i];
 }
 
 // Zero the look-back state: tile status words, the ticket counter and the
@@ -323,7 +329,7 @@ int64_t setop_tiles(int64_t n) { return (n + kSetTMin - 1) / kSetTMin; }
 
 template <typename K>
 hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb, K *S,
-                         int64_t *count, int64_t *ws, hipStream_t s) {
+                         int64_t cap, int64_t *count, int64_t *ws, hipStream_t s) {
   constexpr int T = kSetNT * kSetVT<K>;
   const int64_t n_tiles = (na + nb + T - 1) / T;  // at most setop_tiles(na + nb)
   int64_t *splits = ws;
@@ -337,7 +343,7 @@ hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb,
   auto run = [&](auto opc) {
     constexpr int OP = decltype(opc)::value;
     hipLaunchKernelGGL((setop_tile_kernel<K, OP>), dim3((unsigned)n_tiles), dim3(kSetNT), 0, s, A,
-                       na, B, nb, splits, status, ticket, n_tiles, count, S);
+                       na, B, nb, splits, status, ticket, n_tiles, count, S, cap);
   };
   switch (op) {
     case 0: run(std::integral_constant<int, 0>()); break;
@@ -351,7 +357,7 @@ hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb,
 
 #define MP_INSTANTIATE(K)                                                               \
   template hipError_t launch_set_op<K>(int, const K *, int64_t, const K *, int64_t, K *, \
-                                       int64_t *, int64_t *, hipStream_t);
+                                       int64_t, int64_t *, int64_t *, hipStream_t);
 MP_INSTANTIATE(uint32_t)
 MP_INSTANTIATE(int32_t)
 MP_INSTANTIATE(uint64_t)

@@ -174,3 +174,16 @@ def test_partition_argument_errors(L):
     assert L.mp_partition(MP_F32, a, 4, b, 4, d, 4, None, None) == INVALID
     assert L.mp_partition(MP_F32, a, 4, b, 4, d, 4, P(0x30000 + 8), None) == OVERLAP
     assert L.mp_partition(MP_F32, a, 4, b, 4, d, 0, o, None) == OK
+
+
+def test_bw_probe_argument_errors(L):
+    s, d = P(0x10000), P(0x20000)
+    assert L.mp_bw_probe(3, s, d, 1024, 0, 0, None) == INVALID
+    assert L.mp_bw_probe(0, s, d, 1000, 0, 0, None) == INVALID        # not a multiple of 16
+    assert L.mp_bw_probe(0, s, d, 1024, 0, -1, None) == INVALID
+    assert L.mp_bw_probe(0, None, d, 1024, 0, 0, None) == INVALID
+    assert L.mp_bw_probe(1, P(0x10008), d, 1024, 0, 8, None) == INVALID  # misaligned
+    assert L.mp_bw_probe(0, s, P(0x10000 + 512), 1024, 0, 0, None) == OVERLAP
+    assert L.mp_bw_probe(1, s, P(0x10000 + 512), 1024, 0, 8, None) == OVERLAP  # sink inside src
+    assert L.mp_bw_probe(0, s, d, 1024, 3, 8, None) in (UNSUPPORTED, -5)  # unroll 3 not built
+    assert L.mp_bw_probe(2, None, d, 0, 0, 0, None) == OK
