@@ -451,6 +451,14 @@ mp_status mp_timing_query(const char *name, double *total_ms, int64_t *launches)
  */
 mp_status mp_stats_query(int64_t *tiles, int64_t *reloads);
 
+/*
+ * Companion counter of mp_stats_query: how many workgroups of the persistent
+ * merge kernels had at least one tile (each walks a contiguous run of tiles,
+ * Corollary 7), so tiles / workgroups is the mean run length.  Same
+ * collection, reset and synchronisation rules.  MP_ERR_INVALID_ARG for NULL.
+ */
+mp_status mp_stats_workgroups(int64_t *groups);
+
 #ifdef __cplusplus
 }
 #endif

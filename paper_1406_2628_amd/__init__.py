@@ -75,6 +75,7 @@ def _declare(L):
         "mp_timing_query": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_int64)], i32),
         "mp_stats_query": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], i32),
+        "mp_stats_workgroups": ([ctypes.POINTER(ctypes.c_int64)], i32),
         "mp_lp_create": ([ctypes.POINTER(p), i32, i32, ctypes.c_uint64], i32),
         "mp_lp_destroy": ([p], None),
         "mp_lp_num_params": ([p], i32),
@@ -173,6 +174,13 @@ def stats_query():
     t, r = ctypes.c_int64(), ctypes.c_int64()
     _check(lib().mp_stats_query(ctypes.byref(t), ctypes.byref(r)))
     return t.value, r.value
+
+
+def stats_workgroups() -> int:
+    """Workgroups of the persistent kernels that had a tile, since the last reset."""
+    g = ctypes.c_int64()
+    _check(lib().mp_stats_workgroups(ctypes.byref(g)))
+    return g.value
 
 
 def last_error() -> str:

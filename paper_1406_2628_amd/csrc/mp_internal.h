@@ -154,7 +154,7 @@ hipError_t run_maybe_graph(std::vector<uint64_t> key, hipStream_t s,
 // Record the message returned by mp_last_error() (this thread) and return st.
 mp_status set_error(mp_status st, const char *fmt, ...);
 
-// Device counters [tiles, window reloads] of the persistent kernels while
+// Device counters [tiles, window reloads, workgroups] of the persistent kernels while
 // timing is enabled, nullptr otherwise.
 unsigned long long *stats_device_ptr();
 

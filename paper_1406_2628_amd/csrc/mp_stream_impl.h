@@ -66,7 +66,7 @@ struct PairArgs {
   int lw;                  // kRuns: log2 of the run width
   const int64_t *a_off, *b_off;  // kExplicit
   int64_t n_pairs;
-  unsigned long long *stats;     // optional: [tiles, window reloads]
+  unsigned long long *stats;     // optional: [tiles, window reloads, workgroups]
   unsigned long long *checksum;  // no-store launches: sum of S[i] * (i + 1) added here
 };
 
@@ -807,6 +807,7 @@ __global__ __launch_bounds__(NT) void merge_pairs_kernel(PairArgs<K> args) {
   if (P.stats && tid == 0) {
     atomicAdd(&P.stats[0], (unsigned long long)(t_end - t_begin));
     atomicAdd(&P.stats[1], n_reload);
+    atomicAdd(&P.stats[2], 1ull);
   }
 }
 

@@ -18,7 +18,7 @@ struct Record {
 std::atomic<bool> g_on{false};
 std::mutex g_mu;
 std::vector<Record> g_records;
-unsigned long long *g_stats = nullptr;  // device: [tiles, window reloads]
+unsigned long long *g_stats = nullptr;  // device: [tiles, window reloads, workgroups]
 int g_stats_dev = -1;
 
 void drop_all() {
@@ -37,11 +37,11 @@ hipError_t reset_stats() {
   if (!g_stats || g_stats_dev != dev) {
     if (g_stats) (void)hipFree(g_stats);
     g_stats = nullptr;
-    e = hipMalloc(&g_stats, 2 * sizeof(unsigned long long));
+    e = hipMalloc(&g_stats, 3 * sizeof(unsigned long long));
     if (e != hipSuccess) return e;
     g_stats_dev = dev;
   }
-  return hipMemset(g_stats, 0, 2 * sizeof(unsigned long long));
+  return hipMemset(g_stats, 0, 3 * sizeof(unsigned long long));
 }
 
 }  // namespace
@@ -100,11 +100,21 @@ mp_status mp_timing_reset(void) {
 mp_status mp_stats_query(int64_t *tiles, int64_t *reloads) {
   if (!tiles || !reloads) return MP_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lock(g_mu);
-  unsigned long long h[2] = {0, 0};
+  unsigned long long h[3] = {0, 0, 0};
   if (g_stats && hipMemcpy(h, g_stats, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
     return MP_ERR_HIP;
   *tiles = (int64_t)h[0];
   *reloads = (int64_t)h[1];
+  return MP_OK;
+}
+
+mp_status mp_stats_workgroups(int64_t *groups) {
+  if (!groups) return MP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  unsigned long long h[3] = {0, 0, 0};
+  if (g_stats && hipMemcpy(h, g_stats, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
+    return MP_ERR_HIP;
+  *groups = (int64_t)h[2];
   return MP_OK;
 }
 

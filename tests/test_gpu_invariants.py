@@ -1,0 +1,278 @@
+"""Output-range invariants on the GPU.
+
+Theorem 5 and Corollary 6: every partition pair writes exactly its own
+contiguous range of S, and the ranges tile S.  So a call must write every
+slot of its output and nothing outside it.  Each output here sits between
+64 KiB guards filled with a byte pattern; after the call the guards must be
+unchanged, and the output itself (filled with a different pattern before
+each of two calls) must equal the oracle's both times, so every slot was
+written and the result does not depend on what the buffer held.
+
+The merges run in the shipped default configuration (no set_config) at
+sizes where each persistent workgroup walks several tiles, so the
+cross-tile window prediction, prefetch, lookahead probes and window reloads
+all meet oracle-checked random data.
+"""
+import numpy as np
+import pytest
+import torch
+
+import mp_inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+GUARD_BYTES = 64 * 1024
+FILLS = (0xA5, 0x3C)
+
+
+@pytest.fixture(scope="module")
+def mp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1406_2628_amd as mp
+    mp.lib()
+    for op in ("merge", "batched", "sort"):
+        mp.set_config(op, None)
+    yield mp
+    mp.timing_enable(False)
+
+
+class Guarded:
+    """A device array of n elements with GUARD_BYTES of pattern on each side."""
+
+    def __init__(self, n, dtype, fill):
+        es = torch.empty(0, dtype=dtype).element_size()
+        self.g = GUARD_BYTES // es
+        self.n = n
+        self.es = es
+        self.buf = torch.empty(n + 2 * self.g, dtype=dtype, device="cuda")
+        self.buf.view(torch.uint8).fill_(fill)
+        self.fill = fill
+        self.view = self.buf[self.g:self.g + n]
+
+    def refill(self, fill):
+        self.buf.view(torch.uint8).fill_(fill)
+        self.fill = fill
+
+    def guards_intact(self):
+        b = self.buf.view(torch.uint8)
+        head = b[: self.g * self.es]
+        tail = b[(self.g + self.n) * self.es:]
+        return bool((head == self.fill).all().item()) and bool((tail == self.fill).all().item())
+
+    def host(self):
+        from gpu_util import host
+        return host(self.view)
+
+
+def _torch_dtype(np_dtype):
+    from gpu_util import NP_TO_TORCH
+    return NP_TO_TORCH[np.dtype(np_dtype)]
+
+
+def _multi_tile_merge(mp, orc, A, B, min_tiles_per_group=4):
+    """Default-configuration merge of (A, B) into a guarded output, twice,
+    with different fills; returns nothing, asserts everything."""
+    from gpu_util import dev, first_mismatch
+    want = orc.merge(A, B)
+    dA, dB = dev(A), dev(B)
+    out = Guarded(len(A) + len(B), _torch_dtype(A.dtype), FILLS[0])
+    for fill in FILLS:
+        out.refill(fill)
+        mp.timing_enable(True)
+        mp.merge(dA, dB, out=out.view)
+        tiles, _ = mp.stats_query()
+        groups = mp.stats_workgroups()
+        mp.timing_enable(False)
+        assert out.guards_intact(), "a store landed outside S"
+        assert first_mismatch(out.host(), want) is None, (A.dtype, len(A), len(B), fill)
+        assert groups > 0 and tiles >= min_tiles_per_group * groups, (tiles, groups)
+
+
+def test_default_merge_u32_uniform_many_tiles_per_group(mp, orc):
+    A, B = gen.uniform_pair(1 << 24, (1 << 24) + 4321, 101)
+    _multi_tile_merge(mp, orc, A, B)
+
+
+def test_default_merge_u32_dups_many_tiles_per_group(mp, orc):
+    A, B = gen.dups_pair(1 << 23, (1 << 23) - 999, 102, hi=1024)
+    _multi_tile_merge(mp, orc, A, B, min_tiles_per_group=2)
+
+
+def test_default_merge_f32_mixture_many_tiles_per_group(mp, orc):
+    A, B = gen.f32_mixture_pair(1 << 23, (1 << 23) + 77, 103)
+    _multi_tile_merge(mp, orc, A, B, min_tiles_per_group=2)
+
+
+def test_default_merge_u64_many_tiles_per_group(mp, orc):
+    A, B = gen.uniform_pair(1 << 23, (1 << 23) + 5, 104, gen.U64)
+    _multi_tile_merge(mp, orc, A, B, min_tiles_per_group=2)
+
+
+@pytest.mark.parametrize("dt,log2n", [(gen.U32, 23), (gen.U64, 22)])
+def test_default_merge_kv_many_tiles_per_group(mp, orc, dt, log2n):
+    """Key-value merges in the default configuration (8-byte keys take their
+    own built-in tile), values = index in A ++ B, so stability is checked."""
+    from gpu_util import dev, first_mismatch
+    n = 1 << log2n
+    A, B = gen.uniform_pair(n, n + 1234, 105, dt)
+    va, vb = gen.index_payload(len(A), len(B))
+    wk, wv = orc.merge_kv(A, va, B, vb)
+    dA, dB, dva, dvb = dev(A), dev(B), dev(va), dev(vb)
+    m = len(A) + len(B)
+    ok = Guarded(m, _torch_dtype(A.dtype), FILLS[0])
+    ov = Guarded(m, _torch_dtype(np.uint32), FILLS[0])
+    for fill in FILLS:
+        ok.refill(fill)
+        ov.refill(fill)
+        mp.timing_enable(True)
+        mp.merge_kv(dA, dva, dB, dvb, out_k=ok.view, out_v=ov.view)
+        tiles, _ = mp.stats_query()
+        groups = mp.stats_workgroups()
+        mp.timing_enable(False)
+        assert ok.guards_intact() and ov.guards_intact()
+        assert first_mismatch(ok.host(), wk) is None
+        assert first_mismatch(ov.host(), wv) is None
+        assert groups > 0 and tiles >= 2 * groups, (tiles, groups)
+
+
+def test_per_tile_mode_guards(mp, orc):
+    """The per-tile merge (mode 1: each workgroup searches its own two
+    splits) over many tiles, keys and key-value."""
+    from gpu_util import dev, first_mismatch
+    A, B = gen.uniform_pair(3_000_017, 2_500_001, 106)
+    va, vb = gen.index_payload(len(A), len(B))
+    wk, wv = orc.merge_kv(A, va, B, vb)
+    dA, dB, dva, dvb = dev(A), dev(B), dev(va), dev(vb)
+    m = len(A) + len(B)
+    for nt, vt in ((256, 16), (256, 8), (128, 16), (256, 15)):
+        mp.set_config("merge", 1, nt, vt)
+        try:
+            out = Guarded(m, _torch_dtype(np.uint32), FILLS[0])
+            ov = Guarded(m, _torch_dtype(np.uint32), FILLS[1])
+            mp.merge(dA, dB, out=out.view)
+            assert out.guards_intact()
+            assert first_mismatch(out.host(), wk) is None, (nt, vt)
+            out.refill(FILLS[1])
+            mp.merge_kv(dA, dva, dB, dvb, out_k=out.view, out_v=ov.view)
+            assert out.guards_intact() and ov.guards_intact()
+            assert first_mismatch(out.host(), wk) is None
+            assert first_mismatch(ov.host(), wv) is None
+        finally:
+            mp.set_config("merge", None)
+
+
+@pytest.mark.parametrize("dt,kv", [(gen.U32, False), (gen.F32, True), (gen.U64, True)])
+def test_sort_guards(mp, orc, dt, kv):
+    """Sort in place inside a guarded buffer, with a guarded workspace."""
+    from gpu_util import first_mismatch
+    n = (1 << 20) + 12_345
+    keys = gen.unsorted_uniform(n, 107, dt)
+    vals = np.arange(n, dtype=np.uint32)
+    kbuf = Guarded(n, _torch_dtype(keys.dtype), FILLS[0])
+    vbuf = Guarded(n, torch.uint32, FILLS[0]) if kv else None
+    vt = torch.uint32 if kv else None
+    ws = Guarded(mp.sort_workspace_bytes(kbuf.view.dtype, vt, n), torch.uint8, FILLS[1])
+    kbuf.view.copy_(torch.from_numpy(keys))
+    if kv:
+        vbuf.view.copy_(torch.from_numpy(vals))
+        mp.sort(kbuf.view, vbuf.view, ws=ws.view)
+    else:
+        mp.sort(kbuf.view, ws=ws.view)
+    assert kbuf.guards_intact() and ws.guards_intact()
+    if kv:
+        assert vbuf.guards_intact()
+        wk, wv = orc.sort(keys, vals)
+        assert first_mismatch(kbuf.host(), wk) is None
+        assert first_mismatch(vbuf.host(), wv) is None
+    else:
+        assert first_mismatch(kbuf.host(), orc.sort(keys)) is None
+
+
+def test_batched_guards(mp, orc):
+    from gpu_util import dev, first_mismatch
+    A, a_off, B, b_off = gen.batched_pairs(3000, 108, median=700.0)
+    want = orc.merge_batched(A, a_off, B, b_off)
+    out = Guarded(len(A) + len(B), _torch_dtype(np.int32), FILLS[0])
+    dA, dB, da, db = dev(A), dev(B), dev(a_off), dev(b_off)
+    for fill in FILLS:
+        out.refill(fill)
+        mp.timing_enable(True)
+        mp.merge_batched(dA, da, dB, db, out=out.view)
+        tiles, _ = mp.stats_query()
+        groups = mp.stats_workgroups()
+        mp.timing_enable(False)
+        assert out.guards_intact()
+        assert first_mismatch(out.host(), want) is None, fill
+        assert tiles >= groups > 0
+
+
+@pytest.mark.parametrize("op", ["intersection", "union", "difference", "symmetric_difference"])
+def test_set_op_guards(mp, orc, op):
+    """The output holds exactly the capacity the header asks for (|A| for
+    intersection and difference, |A| + |B| otherwise)."""
+    from gpu_util import dev, host
+    g = np.random.default_rng(109)
+    A = np.sort(g.integers(0, 1 << 21, 1_000_003)).astype(np.uint32)
+    B = np.sort(g.integers(0, 1 << 21, 900_007)).astype(np.uint32)
+    want = orc.set_op(op, A, B)
+    cap = len(A) if op in ("intersection", "difference") else len(A) + len(B)
+    out = Guarded(cap, torch.uint32, FILLS[0])
+    cnt = Guarded(1, torch.int64, FILLS[1])
+    got, count = mp.set_op(op, dev(A), dev(B), out=out.view, count=cnt.view, sync=False)
+    k = int(host(count)[0])
+    assert out.guards_intact() and cnt.guards_intact()
+    assert k == len(want)
+    assert out.host()[:k].tobytes() == want.tobytes()
+
+
+def test_merge_split_wrong_splits_stay_inside_s(mp, orc):
+    """Splits that are not the true ones (huge, negative, decreasing, random)
+    give some other output, but never a store outside S."""
+    from gpu_util import dev
+    A, B = gen.uniform_pair(30_001, 20_011, 110)
+    n = len(A) + len(B)
+    k = (n + 4095) // 4096 + 1
+    g = np.random.default_rng(111)
+    dA, dB = dev(A), dev(B)
+    for sp in (np.full(k, 1 << 62, np.int64), np.full(k, -5, np.int64),
+               np.arange(k, dtype=np.int64)[::-1].copy() * 4096, g.integers(-n, 2 * n, k)):
+        out = Guarded(n, torch.uint32, FILLS[0])
+        mp.merge_split(dA, dB, dev(sp), 4096, out=out.view)
+        assert out.guards_intact()
+
+
+def test_partition_guards(mp, orc):
+    from gpu_util import dev, first_mismatch
+    A, B = gen.uniform_pair(500_001, 400_003, 112)
+    d = np.sort(np.random.default_rng(113).integers(0, len(A) + len(B) + 1, 70_001)).astype(np.int64)
+    out = Guarded(len(d), torch.int64, FILLS[0])
+    mp.partition(dev(A), dev(B), dev(d), out=out.view)
+    assert out.guards_intact()
+    assert first_mismatch(out.host(), orc.partition(A, B, d)) is None
+
+
+@pytest.mark.parametrize("op", ["intersection", "union", "difference", "symmetric_difference"])
+def test_set_op_unsorted_inputs_stay_inside_s(mp, op):
+    """Sortedness is a precondition: violating it gives unspecified output,
+    but no store past S's room.  The first case makes non-monotone splits,
+    so without the room bound the tiles of a difference would together keep
+    three times |A| keys: A = [1] * T + [10] * T, B = [5] * T + [0] * T with
+    T = 12288 (one 4-byte-key tile)."""
+    from gpu_util import dev, host
+    T = 12288
+    A = np.concatenate([np.full(T, 1, np.uint32), np.full(T, 10, np.uint32)])
+    B = np.concatenate([np.full(T, 5, np.uint32), np.full(T, 0, np.uint32)])
+    g = np.random.default_rng(114)
+    cases = [(A, B), (g.integers(0, 50, 100_003).astype(np.uint32),
+                      g.integers(0, 50, 90_001).astype(np.uint32)),
+             (np.sort(g.integers(0, 1000, 80_000)).astype(np.uint32)[::-1].copy(),
+              np.sort(g.integers(0, 1000, 70_000)).astype(np.uint32))]
+    for A_, B_ in cases:
+        cap = len(A_) if op in ("intersection", "difference") else len(A_) + len(B_)
+        out = Guarded(cap, torch.uint32, FILLS[0])
+        cnt = Guarded(1, torch.int64, FILLS[1])
+        _, count = mp.set_op(op, dev(A_), dev(B_), out=out.view, count=cnt.view, sync=False)
+        k = int(host(count)[0])
+        assert out.guards_intact() and cnt.guards_intact(), (op, len(A_), len(B_))
+        assert 0 <= k <= cap, (k, cap)

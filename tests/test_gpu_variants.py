@@ -53,16 +53,32 @@ def test_merge_variants(mp, orc, variant):
 @pytest.mark.parametrize("vt", [8, 12])
 def test_speculative_window_margins(mp, orc, margin, vt):
     """Tiny margins force the exact full-window reload on almost every tile;
-    -1 disables speculation.  Every setting must give the oracle's bits."""
+    -1 disables speculation.  Every setting must give the oracle's bits.
+    The grid is 8 workgroups, so each walks dozens of tiles and every tile
+    after its first merges from windows sized (or reloaded) from the tile
+    before it."""
     from gpu_util import dev, host, first_mismatch
-    mp.set_config("merge", 2, 256, vt, 0, margin)
+    grid = 8
+    mp.set_config("merge", 2, 256, vt, grid, margin)
     try:
         cases = [gen.uniform_pair(200_003, 150_001, 31), gen.dups_pair(180_001, 170_003, 32, hi=40),
                  gen.disjoint_pair(120_000, 90_001, 33), gen.uniform_pair(7, 300_000, 34),
                  gen.uniform_pair(300_000, 7, 35)]
-        for A, B in cases:
+        for i, (A, B) in enumerate(cases):
+            mp.timing_enable(True)
             got = host(mp.merge(dev(A), dev(B)))
+            tiles, reloads = mp.stats_query()
+            groups = mp.stats_workgroups()
+            mp.timing_enable(False)
             assert first_mismatch(got, orc.merge(A, B)) is None, (len(A), len(B), margin)
+            assert groups == grid and tiles == -(-(len(A) + len(B)) // (256 * vt)), (tiles, groups)
+            assert tiles >= 6 * groups
+            if margin < 0:
+                assert reloads == 0, reloads          # full windows never miss
+            if margin == 1 and i == 0:
+                # uniform keys: the A/B mix of a tile wanders by about
+                # sqrt(T) keys, so a one-key margin misses on most tiles
+                assert reloads > (tiles - groups) // 2, (reloads, tiles)
         A, B = gen.dups_pair(100_001, 90_007, 36, hi=30)
         va, vb = gen.index_payload(len(A), len(B))
         gk, gv = mp.merge_kv(dev(A), dev(va), dev(B), dev(vb))
@@ -70,6 +86,7 @@ def test_speculative_window_margins(mp, orc, margin, vt):
         assert first_mismatch(host(gk), wk) is None
         assert first_mismatch(host(gv), wv) is None
     finally:
+        mp.timing_enable(False)
         mp.set_config("merge", None)
 
 
