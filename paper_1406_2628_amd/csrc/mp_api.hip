@@ -52,12 +52,17 @@ mp_status check_array(const void *p, int64_t n, size_t es, const char *name) {
 
 enum Op { kOpMerge = 0, kOpBatched = 1, kOpSort = 2, kNumOps = 3 };
 
-// Built-in variant per operation (chosen from measurements on MI355X).
+// Built-in variant per operation (chosen from measurements on MI355X):
+// merges and sort rounds per tile with the tile picked from the size (nt = vt
+// = 0), batches persistent.
 const mp_config kDefaultConfig[kNumOps] = {
-    {2, 192, 24, 0, 0},  // merge
+    {1, 0, 0, 0, 0},     // merge
     {2, 256, 16, 0, 0},  // batched
-    {2, 256, 16, 0, 0},  // sort rounds
+    {1, 0, 0, 0, 0},     // sort rounds
 };
+// The persistent shape the no-store diagnostic uses when the merge is not
+// set to a persistent shape that has a no-store variant.
+const mp_config kChecksumConfig = {2, 192, 24, 0, 0};
 mp_config g_config[kNumOps] = {kDefaultConfig[0], kDefaultConfig[1], kDefaultConfig[2]};
 // Whether g_config[op] was chosen (mp_set_config or the autotuner) rather
 // than being the built-in choice.
@@ -83,6 +88,24 @@ mp_status set_error(mp_status st, const char *fmt, ...) {
   vsnprintf(g_err, sizeof g_err, fmt, ap);
   va_end(ap);
   return st;
+}
+
+// Largest tile of the key's ladder that still leaves at least two tiles per
+// compute unit (smaller tiles only for small merges).  The ladders keep a
+// tile's LDS at or under 64 KB (two workgroups per compute unit): 16384 keys
+// of 4 bytes, 8192 of 8 bytes or of 4 bytes with values, 4096 of 8 bytes
+// with values.
+TileCfg auto_tile_cfg(size_t key_bytes, bool kv, int64_t n) {
+  static const TileCfg k4[] = {{1024, 16}, {512, 16}, {256, 16}, {256, 8}};
+  static const TileCfg k4v[] = {{1024, 8}, {256, 16}, {256, 8}};
+  static const TileCfg k8[] = {{1024, 8}, {256, 16}, {256, 8}};
+  static const TileCfg k8v[] = {{256, 16}, {256, 8}};
+  const TileCfg *lad = key_bytes == 8 ? (kv ? k8v : k8) : (kv ? k4v : k4);
+  const int len = key_bytes == 8 ? (kv ? 2 : 3) : (kv ? 3 : 4);
+  const int64_t want = 2 * (int64_t)device_cu_count();
+  for (int i = 0; i < len; ++i)
+    if (n / ((int64_t)lad[i].nt * lad[i].vt) >= want) return lad[i];
+  return lad[len - 1];
 }
 
 int device_cu_count() {
@@ -167,25 +190,17 @@ static mp_status merge_common(const char *fn, mp_dtype kt, mp_dtype vt,
   if (n == 0) return MP_OK;
 
   hipStream_t s = (hipStream_t)stream;
-  mp_config cfg = current_config(kOpMerge);
-  // Built-in choice with values and 8-byte keys: values make a tile's LDS
-  // 1.5 times that of the keys, which at the default tile leaves one
-  // workgroup per compute unit; 256 x 12 keeps two (18% faster on 2^27 +
-  // 2^27 u64 with values).
-  if (kv && es == 8 && !g_config_chosen[kOpMerge]) {
-    cfg.nt = 256;
-    cfg.vt = 12;
-  }
+  const mp_config cfg = current_config(kOpMerge);
   hipError_t e = hipSuccess;
   if (cfg.mode == 1) {
-    // one workgroup per tile, each finding its own two splits
-    const TileCfg tc{cfg.nt, cfg.vt};
+    // split search on the tile diagonals, then one workgroup per tile
+    const TileCfg tc = cfg.nt > 0 ? TileCfg{cfg.nt, cfg.vt} : auto_tile_cfg(es, kv, n);
     dispatch_key(kt, [&](auto k) {
       using K = decltype(k);
       KernelTimer timer("merge_tiles", s);
       e = launch_merge_tiles<K>(tc, (const K *)Ak, (const uint32_t *)Av, na,
                                 (const K *)Bk, (const uint32_t *)Bv, nb, (K *)Sk,
-                                kv ? (uint32_t *)Sv : nullptr, nullptr, s);
+                                kv ? (uint32_t *)Sv : nullptr, s);
     });
   } else {
     const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
@@ -255,10 +270,12 @@ mp_status mp_merge_split(mp_dtype kt, const void *A, int64_t na, const void *B, 
   const char *fn = "mp_merge_split";
   if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported key dtype %d", fn, (int)kt);
   TileCfg tc{0, 0};
-  if (tile == 4096) tc = {256, 16};
+  if (tile == 16384) tc = {1024, 16};
+  else if (tile == 8192) tc = {512, 16};
+  else if (tile == 4096) tc = {256, 16};
   else if (tile == 3840) tc = {256, 15};
   else if (tile == 2048) tc = {256, 8};
-  else return fail(MP_ERR_UNSUPPORTED, "%s: tile must be 2048, 3840 or 4096", fn);
+  else return fail(MP_ERR_UNSUPPORTED, "%s: tile must be 2048, 3840, 4096, 8192 or 16384", fn);
   const size_t es = dtype_size(kt);
   mp_status st;
   if ((st = check_array(A, na, es, "A")) != MP_OK) return st;
@@ -278,9 +295,10 @@ mp_status mp_merge_split(mp_dtype kt, const void *A, int64_t na, const void *B, 
   dispatch_key(kt, [&](auto k) {
     using K = decltype(k);
     KernelTimer timer("merge_tiles", s);
-    e = launch_merge_tiles<K>(tc, (const K *)A, nullptr, na, (const K *)B, nullptr, nb, (K *)S,
-                              nullptr, a_split, s);
+    e = launch_merge_tiles_split<K>(tc, (const K *)A, na, (const K *)B, nb, (K *)S, a_split, s);
   });
+  if (e == hipErrorNotSupported)
+    return fail(MP_ERR_UNSUPPORTED, "%s: tile %d is not built for this key type", fn, tile);
   return e == hipSuccess ? MP_OK : hip_fail(e, "mp_merge_split launch");
 }
 
@@ -301,9 +319,9 @@ mp_status mp_merge_checksum(mp_dtype kt, const void *A, int64_t na, const void *
   if (na + nb == 0) return MP_OK;
   mp_config cfg = current_config(kOpMerge);
   // the persistent kernel with the merge's tile when it has a no-store
-  // variant, else the built-in tile
+  // variant, else 192 x 24
   if (cfg.mode != 2 || !((cfg.nt == 192 && cfg.vt == 24) || (cfg.nt == 256 && cfg.vt == 16))) {
-    cfg = kDefaultConfig[kOpMerge];
+    cfg = kChecksumConfig;
   }
   const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
   hipStream_t s = (hipStream_t)stream;
@@ -332,16 +350,21 @@ mp_status mp_set_config(const char *op, const mp_config *cfg) {
     g_config_chosen[i] = false;
     return MP_OK;
   }
-  if ((cfg->mode != 1 && cfg->mode != 2) || cfg->nt <= 0 || cfg->vt <= 0 || cfg->grid < 0)
+  // mode 1 takes nt = vt = 0 for the tile picked from each call's size
+  const bool auto_tile = cfg->mode == 1 && cfg->nt == 0 && cfg->vt == 0;
+  if ((cfg->mode != 1 && cfg->mode != 2) || cfg->grid < 0 ||
+      (!auto_tile && (cfg->nt <= 0 || cfg->vt <= 0)))
     return fail(MP_ERR_INVALID_ARG, "mp_set_config: invalid configuration");
-  if (cfg->mode == 1 && i != kOpMerge)
-    return fail(MP_ERR_UNSUPPORTED, "mp_set_config: per-tile mode exists for merge only");
-  if (i == kOpSort) {
-    // merge rounds rely on tiles that divide every run pair (2w >= 2 blocks)
+  if (cfg->mode == 1 && i == kOpBatched)
+    return fail(MP_ERR_UNSUPPORTED, "mp_set_config: per-tile mode exists for merge and sort only");
+  if (i == kOpSort && !auto_tile) {
+    // merge rounds rely on tiles that divide every run pair (2w >= 2 blocks;
+    // persistent rounds as built assume the smallest block of 4096)
     const int64_t t = (int64_t)cfg->nt * cfg->vt;
-    if ((t & (t - 1)) != 0 || t > (2 << kSortBlockMinLog2))
-      return fail(MP_ERR_UNSUPPORTED, "mp_set_config: sort tiles must be a power of two <= %d",
-                  2 << kSortBlockMinLog2);
+    const int64_t lim = cfg->mode == 1 ? (int64_t)2 << 13 : (int64_t)2 << kSortBlockMinLog2;
+    if ((t & (t - 1)) != 0 || t > lim)
+      return fail(MP_ERR_UNSUPPORTED, "mp_set_config: sort tiles must be a power of two <= %lld",
+                  (long long)lim);
   }
   g_config[i] = *cfg;
   g_config_chosen[i] = true;
@@ -481,6 +504,10 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
   const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
   hipStream_t s = (hipStream_t)stream;
   const int lb = sort_block_log2(es, kv);
+  const TileCfg tc = cfg.nt > 0 ? TileCfg{cfg.nt, cfg.vt} : auto_tile_cfg(es, kv, n);
+  if (cfg.mode == 1 && (int64_t)tc.nt * tc.vt > ((int64_t)2 << lb))
+    return fail(MP_ERR_UNSUPPORTED, "%s: tile %d x %d does not divide a run pair of %lld keys", fn,
+                tc.nt, tc.vt, (long long)((int64_t)2 << lb));
   int rounds = 0;
   for (int64_t w = (int64_t)1 << lb; w < n; w <<= 1) ++rounds;
   const std::vector<uint64_t> key = {
@@ -504,7 +531,10 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
       }
       for (int lw = lb; ee == hipSuccess && ((int64_t)1 << lw) < n; ++lw) {
         KernelTimer timer("sort_round", st);
-        ee = launch_sort_round<K>(sc, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, lw, st);
+        if (cfg.mode == 1)
+          ee = launch_sort_round_tiles<K>(tc, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, lw, st);
+        else
+          ee = launch_sort_round<K>(sc, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, lw, st);
         cur ^= 1;
       }
     });
@@ -527,6 +557,9 @@ mp_status mp_sort(mp_dtype kt, mp_dtype vt, void *keys, void *vals, int64_t n,
 
 static const int kTuneShapes[][2] = {{192, 24}, {256, 16}, {256, 18}, {256, 14}, {256, 12},
                                      {256, 8},  {128, 16}, {512, 8},   {512, 16}};
+// per-tile shapes (merge and sort)
+static const int kTuneTileShapes[][2] = {{1024, 16}, {1024, 8}, {512, 16}, {512, 12},
+                                         {256, 16},  {256, 8}};
 
 template <typename Run, typename Setup>
 static mp_status autotune(Op op, int reps, hipStream_t s, Run run, Setup setup, mp_config *best) {
@@ -573,7 +606,19 @@ static mp_status autotune(Op op, int reps, hipStream_t s, Run run, Setup setup, 
     }
   };
   const int cus = device_cu_count();
+  if (op != kOpBatched) {
+    for (const auto &shape : kTuneTileShapes) {
+      const mp_config c{1, shape[0], shape[1], 0, 0};
+      if (op == kOpSort) {
+        const int64_t t = (int64_t)c.nt * c.vt;
+        if ((t & (t - 1)) != 0) continue;
+      }
+      consider(c, time_config(c));
+      if (st != MP_OK) break;
+    }
+  }
   for (const auto &shape : kTuneShapes) {
+    if (st != MP_OK) break;
     mp_config c{2, shape[0], shape[1], 0, 0};
     if (op == kOpSort) {
       const int64_t t = (int64_t)c.nt * c.vt;

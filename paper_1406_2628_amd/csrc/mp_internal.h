@@ -52,17 +52,30 @@ hipError_t launch_partition(const K *A, int64_t na, const K *B, int64_t nb,
                             const int64_t *diag, int64_t tile, int64_t n_diag,
                             int64_t *a_split, hipStream_t s);
 
-// Per-tile merge of T = nt * vt outputs per workgroup, given the splits of
-// every tile boundary (n_tiles + 1 entries), or with a_split == nullptr
-// finding each tile's two splits inside its own workgroup.  Av/Bv/Sv may be
-// null (keys only).
+// Per-tile merge (Algorithm 1) of T = nt * vt outputs per workgroup: the
+// splits of every tile boundary are found first and handed to each tile in
+// the first 32 bytes of its own range of S, then one workgroup per tile
+// merges its pair.  Av/Bv/Sv may be null (keys only).  hipErrorNotSupported
+// for a shape that is not built for the key type.
 template <typename K>
 hipError_t launch_merge_tiles(TileCfg cfg, const K *A, const uint32_t *Av,
                               int64_t na, const K *B, const uint32_t *Bv,
-                              int64_t nb, K *S, uint32_t *Sv,
-                              const int64_t *a_split, hipStream_t s);
+                              int64_t nb, K *S, uint32_t *Sv, hipStream_t s);
 
-TileCfg default_tile_cfg(size_t key_bytes, bool kv);
+// The tile merge on the caller's splits of the tile diagonals (keys only).
+template <typename K>
+hipError_t launch_merge_tiles_split(TileCfg cfg, const K *A, int64_t na, const K *B,
+                                    int64_t nb, K *S, const int64_t *a_split, hipStream_t s);
+
+// One merge-sort round through the per-tile merge: runs of width 2^lw in X
+// merged pairwise into Y; the tile (a power of two) must divide 2^(lw+1).
+template <typename K>
+hipError_t launch_sort_round_tiles(TileCfg cfg, const K *X, const uint32_t *Xv, K *Y,
+                                   uint32_t *Yv, int64_t n, int lw, hipStream_t s);
+
+// Built-in per-tile shape for n outputs of a key size, with or without
+// values: the largest tile that still gives every compute unit a few tiles.
+TileCfg auto_tile_cfg(size_t key_bytes, bool kv, int64_t n);
 
 // Persistent merge: nt lanes x vt outputs per tile, `grid` workgroups each
 // walking a contiguous run of tiles (0 = one full wave of resident groups).

@@ -1,0 +1,470 @@
+// Per-tile merge: Algorithm 1 with one workgroup per output tile.
+//
+// Step 1 (tile_splits_kernel): the split on every tile boundary diagonal
+// k * T is found by Algorithm 2 (one lane, or a group of lanes cutting the
+// interval more ways per round, per diagonal; Theorem 14 bounds the rounds).
+// Step 2 (merge_tile_kernel): each workgroup takes the pair that its two
+// splits cut out of A and B (Theorem 5: it merges to exactly the tile's
+// range of S), stages it in LDS with 16-byte loads, finds every lane's split
+// at local diagonal lane * VT inside it (Theorem 17), merges VT outputs per
+// lane in registers (Lemma 1; ties take A) and writes the tile through an
+// LDS transpose with 16-byte stores.
+//
+// The splits travel from step 1 to step 2 inside S itself: tile k's pair
+// (a0, b0, a1, b1) is written into the first 32 bytes of tile k's own output
+// range, which no other tile reads or writes; tile k's workgroup reads them
+// before it stores anything there.  So the merge needs no memory beyond its
+// inputs and output, and concurrent calls on different streams share
+// nothing.  A last tile shorter than 32 bytes gets no header; its end split
+// is the end of the grid (or of its run pair), and its start split is found
+// by stepping the path backwards from there (fewer than 8 steps).
+//
+// Layouts: kSingle merges (A, B); kRuns is one round of merge sort over X:
+// pair k is (X[2wk, 2wk+w), X[2wk+w, 2wk+2w)) clipped to n, left run as A
+// (stable), and tiles (a power of two dividing 2w) never cross a pair end,
+// so every tile is again one plain pair of ranges of X.
+#pragma once
+
+#include "mp_device.h"
+#include "mp_internal.h"
+
+namespace mp {
+
+enum TileKind { kTileSingle = 0, kTileRuns = 1 };
+enum TileSrc { kTileHeader = 0, kTileSplitArray = 1 };
+
+template <typename K>
+struct TileArgs {
+  const K *A, *B;           // kTileRuns: both are X
+  const uint32_t *Av, *Bv;  // values (key-value merges only)
+  K *S;
+  uint32_t *Sv;
+  int64_t NA, NB;           // lengths of A and B (kTileRuns: n and n)
+  int64_t N;                // outputs (kTileSingle: NA + NB; kTileRuns: n)
+  int lw;                   // kTileRuns: log2 of the run width
+  const int64_t *a_split;   // kTileSplitArray: the caller's splits
+  int64_t n_tiles;
+};
+
+// Header bytes at the start of each tile's range of S.
+constexpr int kTileHdrBytes = 32;
+
+template <typename K>
+__device__ __forceinline__ void put_tile_hdr(K *S, int64_t d, int slot, int64_t a, int64_t b) {
+  uint32_t *w = reinterpret_cast<uint32_t *>(S + d) + 4 * slot;
+  w[0] = (uint32_t)a;
+  w[1] = (uint32_t)((uint64_t)a >> 32);
+  w[2] = (uint32_t)b;
+  w[3] = (uint32_t)((uint64_t)b >> 32);
+}
+
+template <typename K>
+__device__ __forceinline__ int64_t tile_bytes(const TileArgs<K> &P, int64_t T, int64_t t) {
+  const int64_t r = P.N - t * T;
+  return (r < T ? r : T) * (int64_t)sizeof(K);
+}
+
+// Run pair of output d in a merge-sort round: its first output P0 and the
+// ranges [P0, aE) (left run, A) and [aE, bE) (right run, B) of X.
+__device__ __forceinline__ void run_pair(int64_t d, int64_t n, int lw, int64_t &P0, int64_t &aE,
+                                         int64_t &bE) {
+  const int64_t w = (int64_t)1 << lw;
+  P0 = (d >> (lw + 1)) << (lw + 1);
+  aE = P0 + w < n ? P0 + w : n;
+  bE = P0 + 2 * w < n ? P0 + 2 * w : n;
+}
+
+// Step 1.  Boundary k = 0 .. n_tiles (diagonal min(k * T, N)); G lanes per
+// boundary.  Writes the split as tile k's start and tile k - 1's end.
+template <typename K, int KIND, int G>
+__global__ __launch_bounds__(256) void tile_splits_kernel(TileArgs<K> P, int64_t T) {
+  const int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) / G;
+  if (k > P.n_tiles) return;  // a group exits as one (G divides 256)
+  const int64_t N = P.N;
+  const int64_t D = k * T < N ? k * T : N;
+  int64_t sa, sb, ea, eb;  // start of tile k, end of tile k - 1
+  auto search = [&](int64_t d, int64_t lo, int64_t hi, auto ga, auto gb) -> int64_t {
+    if constexpr (G == 1) return split_search<int64_t>(d, lo, hi, ga, gb);
+    else return group_split_search<G, int64_t>(d, lo, hi, ga, gb);
+  };
+  if constexpr (KIND == kTileSingle) {
+    int64_t lo, hi;
+    diag_range<int64_t>(D, P.NA, P.NB, lo, hi);
+    const K *A = P.A, *B = P.B;
+    sa = search(D, lo, hi, [&](int64_t i) { return A[i]; }, [&](int64_t j) { return B[j]; });
+    sb = D - sa;
+    ea = sa;
+    eb = sb;
+  } else {
+    const K *X = P.A;
+    const int64_t w = (int64_t)1 << P.lw;
+    int64_t P0, aE, bE;
+    if (D == N) {
+      // end of the last pair
+      run_pair(N - 1, N, P.lw, P0, aE, bE);
+      sa = ea = aE;
+      sb = eb = bE;
+    } else {
+      run_pair(D, N, P.lw, P0, aE, bE);
+      const int64_t dl = D - P0;
+      int64_t lo, hi;
+      diag_range<int64_t>(dl, aE - P0, bE - aE, lo, hi);
+      const int64_t a = search(dl, lo, hi, [&](int64_t i) { return X[P0 + i]; },
+                               [&](int64_t j) { return X[aE + j]; });
+      sa = P0 + a;
+      sb = aE + (dl - a);
+      if (D == P0 && D > 0) {
+        // tile k - 1 ends its own pair: that pair's two run ends
+        ea = P0 - w;
+        eb = P0;
+      } else {
+        ea = sa;
+        eb = sb;
+      }
+    }
+  }
+  if constexpr (G > 1) {
+    if ((threadIdx.x & (G - 1)) != 0) return;
+  }
+  if (k < P.n_tiles && tile_bytes(P, T, k) >= kTileHdrBytes) put_tile_hdr(P.S, k * T, 0, sa, sb);
+  if (k > 0 && tile_bytes(P, T, k - 1) >= kTileHdrBytes) put_tile_hdr(P.S, (k - 1) * T, 1, ea, eb);
+}
+
+// Chunk of CH elements at src + g: one vector access when the chunk lies
+// inside the array (lim elements), element loads for the part inside else.
+template <typename T, int CH>
+__device__ __forceinline__ void tile_load_chunk(const T *__restrict__ src, int64_t g, int64_t lim,
+                                                T (&v)[CH]) {
+  if (g + CH <= lim) {
+    if constexpr (CH * sizeof(T) == 16) {
+      *reinterpret_cast<u32x4 *>(v) = *reinterpret_cast<const u32x4 *>(src + g);
+    } else if constexpr (CH * sizeof(T) == 8) {
+      *reinterpret_cast<uint2 *>(v) = *reinterpret_cast<const uint2 *>(src + g);
+    } else {
+#pragma unroll
+      for (int i = 0; i < CH; ++i) v[i] = src[g + i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) v[i] = g + i < lim ? src[g + i] : T{};
+  }
+}
+
+template <typename T, int CH>
+__device__ __forceinline__ void tile_put_chunk(T *lds, const T (&v)[CH]) {
+  if constexpr (CH * sizeof(T) == 16) {
+    *reinterpret_cast<u32x4 *>(lds) = *reinterpret_cast<const u32x4 *>(v);
+  } else if constexpr (CH * sizeof(T) == 8) {
+    *reinterpret_cast<uint2 *>(lds) = *reinterpret_cast<const uint2 *>(v);
+  } else {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) lds[i] = v[i];
+  }
+}
+
+// LDS of one tile: keys (and values) of both windows, in chunks, plus the
+// slack the unguarded tail of the serial merge may read.
+template <typename K, bool KV, int NT, int VT, bool VLOAD>
+struct TileLds {
+  static constexpr int T = NT * VT;
+  static constexpr int CH = VLOAD ? 16 / (int)sizeof(K) : 1;
+  static constexpr int N_KEYS = T + 4 * CH + VT + 1;
+  static constexpr int N_VALS = KV ? T + 4 * CH : 1;
+  static constexpr size_t bytes = (size_t)N_KEYS * sizeof(K) + (size_t)N_VALS * 4;
+};
+// Tile shapes needing more than 96 KB of LDS are not built.
+template <typename K, bool KV, int NT, int VT>
+constexpr bool tile_shape_fits() {
+  return TileLds<K, KV, NT, VT, true>::bytes <= 96 * 1024;
+}
+
+// Step 2.  One workgroup per tile.
+template <typename K, bool KV, int NT, int VT, int KIND, int SRC, bool VLOAD>
+__global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
+  using L = TileLds<K, KV, NT, VT, VLOAD>;
+  constexpr int T = L::T, CH = L::CH;
+  __shared__ __attribute__((aligned(16))) K keys[L::N_KEYS];
+  __shared__ __attribute__((aligned(16))) uint32_t vals[L::N_VALS];
+  const int tid = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t N = P.N, NA = P.NA, NB = P.NB;
+  const int64_t d0 = tile * T;
+  const int n = (int)(N - d0 < T ? N - d0 : T);
+
+  // ---- the tile's pair --------------------------------------------------
+  int64_t a0, b0, a1;
+  if constexpr (SRC == kTileSplitArray) {
+    // the caller's splits: a0 kept on the start diagonal inside the grid and
+    // the A count in its valid range, whatever the values (for the true
+    // splits of sorted inputs both clamps change nothing)
+    a0 = P.a_split[tile];
+    a1 = P.a_split[tile + 1];
+    const int64_t lo0 = d0 > NB ? d0 - NB : 0, hi0 = d0 < NA ? d0 : NA;
+    a0 = a0 < lo0 ? lo0 : (a0 > hi0 ? hi0 : a0);
+    b0 = d0 - a0;
+  } else if ((int64_t)n * (int64_t)sizeof(K) >= kTileHdrBytes) {
+    const uint32_t *h = reinterpret_cast<const uint32_t *>(P.S + d0);
+    a0 = (int64_t)(((uint64_t)h[1] << 32) | h[0]);
+    b0 = (int64_t)(((uint64_t)h[3] << 32) | h[2]);
+    a1 = (int64_t)(((uint64_t)h[5] << 32) | h[4]);
+  } else {
+    // last tile, shorter than a header: from the end of the grid (or of its
+    // run pair) step the path back n times; each step takes the larger of
+    // the two keys before the cursor, B on ties (ties went to A forwards)
+    int64_t alo = 0, blo = 0, ia = NA, ib = NB;
+    if constexpr (KIND == kTileRuns) {
+      int64_t P0, aE, bE;
+      run_pair(d0, N, P.lw, P0, aE, bE);
+      alo = P0;
+      blo = aE;
+      ia = aE;
+      ib = bE;
+    }
+    a1 = ia;
+    for (int s = 0; s < n; ++s) {
+      const bool ta = ia > alo && (ib <= blo || P.B[ib - 1] < P.A[ia - 1]);
+      if (ta) --ia; else --ib;
+    }
+    a0 = ia;
+    b0 = ib;
+  }
+  // keep every access inside the arrays (no-ops for consistent pairs)
+  a0 = a0 < 0 ? 0 : (a0 > NA ? NA : a0);
+  b0 = b0 < 0 ? 0 : (b0 > NB ? NB : b0);
+  int64_t wa64 = a1 - a0;
+  const int64_t wa_hi = NA - a0 < (int64_t)n ? NA - a0 : (int64_t)n;
+  const int64_t wa_lo0 = (int64_t)n - (NB - b0);
+  const int64_t wa_lo = wa_lo0 > 0 ? wa_lo0 : 0;
+  wa64 = wa64 < wa_lo ? wa_lo : wa64;
+  wa64 = wa64 > wa_hi ? wa_hi : wa64;
+  const int wa = (int)wa64;
+  const int wb0 = n - wa;
+  const int wb = (int64_t)wb0 <= NB - b0 ? wb0 : (int)(NB - b0);
+
+  // ---- stage the pair in LDS --------------------------------------------
+  // A's chunks first (from the chunk holding A[a0]), then B's; every lane
+  // issues all its loads before its first LDS write.
+  const int sa = (int)(a0 & (CH - 1)), sb = (int)(b0 & (CH - 1));
+  const int ca = (sa + wa + CH - 1) / CH, cb = (sb + wb + CH - 1) / CH;
+  const int64_t abase = a0 - sa, bbase = b0 - sb;
+  const int pa = sa, pb = ca * CH + sb;  // LDS positions of A[a0] and B[b0]
+  {
+    constexpr int PV = (T / CH + 4 + NT - 1) / NT;
+    K rk[PV][CH];
+    uint32_t rv[KV ? PV : 1][CH];
+#pragma unroll
+    for (int k = 0; k < PV; ++k) {
+      const int c = tid + k * NT;
+      if (c < ca + cb) {
+        const bool fb = c >= ca;
+        const int64_t g = fb ? bbase + (int64_t)(c - ca) * CH : abase + (int64_t)c * CH;
+        const int64_t lim = fb ? NB : NA;
+        tile_load_chunk<K, CH>(fb ? P.B : P.A, g, lim, rk[k]);
+        if constexpr (KV) tile_load_chunk<uint32_t, CH>(fb ? P.Bv : P.Av, g, lim, rv[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < PV; ++k) {
+      const int c = tid + k * NT;
+      if (c < ca + cb) {
+        tile_put_chunk<K, CH>(keys + c * CH, rk[k]);
+        if constexpr (KV) tile_put_chunk<uint32_t, CH>(vals + c * CH, rv[k]);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- lane split and serial merge ---------------------------------------
+  const int dl = tid * VT < n ? tid * VT : n;
+  int lo, hi;
+  diag_range<int>(dl, wa, wb, lo, hi);
+  const int a = split_search<int>(
+      dl, lo, hi, [&](int i) { return keys[pa + i]; }, [&](int j) { return keys[pb + j]; });
+  const int steps = n - dl < VT ? n - dl : VT;
+  K out[VT];
+  int src[VT];
+  serial_merge<K, VT>(keys, pa + a, pb + (dl - a), pa + wa, pb + wb, out, src);
+  uint32_t ov[KV ? VT : 1];
+  if constexpr (KV) {
+    // (past a short lane's run, src may point beyond the staged values)
+#pragma unroll
+    for (int i = 0; i < VT; ++i) ov[i] = i < steps ? vals[src[i]] : 0u;
+  }
+  __syncthreads();
+
+  // ---- LDS transpose and coalesced stores --------------------------------
+  constexpr int RUN_BYTES = VT * (int)sizeof(K);
+  if (RUN_BYTES % 16 == 0 && n == T) {
+#pragma unroll
+    for (int i = 0; i < VT; i += 16 / (int)sizeof(K))
+      *reinterpret_cast<u32x4 *>(keys + tid * VT + i) = *reinterpret_cast<const u32x4 *>(out + i);
+  } else {
+#pragma unroll
+    for (int i = 0; i < VT; ++i)
+      if (i < steps) keys[tid * VT + i] = out[i];
+  }
+  if constexpr (KV) {
+    if ((VT * 4) % 16 == 0 && n == T) {
+#pragma unroll
+      for (int i = 0; i < VT; i += 4)
+        *reinterpret_cast<u32x4 *>(vals + tid * VT + i) = *reinterpret_cast<const u32x4 *>(ov + i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < VT; ++i)
+        if (i < steps) vals[tid * VT + i] = ov[i];
+    }
+  }
+  __syncthreads();
+  constexpr int VEC = 16 / (int)sizeof(K);
+  K *S = P.S + d0;
+  const bool vs = ((uintptr_t)S % 16) == 0;
+  const int nv = vs ? n / VEC : 0;
+  if (n == T && vs) {
+    constexpr int KVN = T / VEC, NK = (KVN + NT - 1) / NT;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+      const int v = tid + j * NT;
+      if (KVN % NT == 0 || v < KVN)
+        __builtin_nontemporal_store(reinterpret_cast<const u32x4 *>(keys)[v],
+                                    reinterpret_cast<u32x4 *>(S) + v);
+    }
+  } else {
+    for (int v = tid; v < nv; v += NT)
+      __builtin_nontemporal_store(reinterpret_cast<const u32x4 *>(keys)[v],
+                                  reinterpret_cast<u32x4 *>(S) + v);
+    for (int i = nv * VEC + tid; i < n; i += NT) S[i] = keys[i];
+  }
+  if constexpr (KV) {
+    uint32_t *Sv = P.Sv + d0;
+    const int nv4 = ((uintptr_t)Sv % 16) == 0 ? n / 4 : 0;
+    for (int v = tid; v < nv4; v += NT)
+      __builtin_nontemporal_store(reinterpret_cast<const u32x4 *>(vals)[v],
+                                  reinterpret_cast<u32x4 *>(Sv) + v);
+    for (int i = nv4 * 4 + tid; i < n; i += NT) Sv[i] = vals[i];
+  }
+}
+
+// ---- launchers ------------------------------------------------------------
+
+template <typename K, int KIND>
+static hipError_t launch_tile_splits(const TileArgs<K> &P, int64_t T, hipStream_t s) {
+  const int64_t n_b = P.n_tiles + 1;
+  const int g = partition_lanes(n_b);
+  const int64_t blocks = (n_b * g + 255) / 256;
+  switch (g) {
+#define MP_SPLITS_CASE(G)                                                                  \
+  case G:                                                                                  \
+    hipLaunchKernelGGL((tile_splits_kernel<K, KIND, G>), dim3((unsigned)blocks), dim3(256), \
+                       0, s, P, T);                                                        \
+    break;
+    MP_SPLITS_CASE(1)
+    MP_SPLITS_CASE(2)
+    MP_SPLITS_CASE(4)
+    MP_SPLITS_CASE(8)
+    MP_SPLITS_CASE(16)
+    MP_SPLITS_CASE(32)
+    MP_SPLITS_CASE(64)
+#undef MP_SPLITS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename K, bool KV, int NT, int VT, int KIND, int SRC>
+static hipError_t launch_tiles_shape(TileArgs<K> P, bool vload, hipStream_t s) {
+  if constexpr (!tile_shape_fits<K, KV, NT, VT>()) {
+    return hipErrorNotSupported;
+  } else {
+    constexpr int64_t T = (int64_t)NT * VT;
+    P.n_tiles = (P.N + T - 1) / T;
+    if (P.n_tiles == 0) return hipSuccess;
+    if constexpr (SRC == kTileHeader) {
+      KernelTimer timer("tile_splits", s);
+      const hipError_t e = launch_tile_splits<K, KIND>(P, T, s);
+      if (e != hipSuccess) return e;
+    }
+    KernelTimer timer("tile_merge", s);
+    if (vload)
+      hipLaunchKernelGGL((merge_tile_kernel<K, KV, NT, VT, KIND, SRC, true>),
+                         dim3((unsigned)P.n_tiles), dim3(NT), 0, s, P);
+    else
+      hipLaunchKernelGGL((merge_tile_kernel<K, KV, NT, VT, KIND, SRC, false>),
+                         dim3((unsigned)P.n_tiles), dim3(NT), 0, s, P);
+    return hipGetLastError();
+  }
+}
+
+template <typename K, int KIND, int SRC>
+static hipError_t launch_tiles_any(TileCfg cfg, const TileArgs<K> &P, bool vload, hipStream_t s) {
+  // (merges on given splits carry keys only)
+  const bool kv = SRC == kTileHeader && P.Sv != nullptr;
+#define MP_TILE_CASE(NT_, VT_)                                                             \
+  if (cfg.nt == NT_ && cfg.vt == VT_) {                                                    \
+    if constexpr (SRC == kTileHeader)                                                      \
+      if (kv) return launch_tiles_shape<K, true, NT_, VT_, KIND, SRC>(P, vload, s);        \
+    return launch_tiles_shape<K, false, NT_, VT_, KIND, SRC>(P, vload, s);                 \
+  }
+  MP_TILE_CASE(1024, 16)
+  MP_TILE_CASE(1024, 8)
+  MP_TILE_CASE(512, 16)
+  MP_TILE_CASE(512, 12)
+  MP_TILE_CASE(256, 16)
+  MP_TILE_CASE(256, 15)
+  MP_TILE_CASE(256, 8)
+  MP_TILE_CASE(128, 16)
+#undef MP_TILE_CASE
+  return hipErrorNotSupported;
+}
+
+static inline bool tile_aligned16(const void *p) { return ((uintptr_t)p % 16) == 0; }
+
+template <typename K>
+hipError_t launch_merge_tiles(TileCfg cfg, const K *A, const uint32_t *Av, int64_t na,
+                              const K *B, const uint32_t *Bv, int64_t nb, K *S, uint32_t *Sv,
+                              hipStream_t s) {
+  TileArgs<K> P{};
+  P.A = A; P.B = B; P.Av = Av; P.Bv = Bv; P.S = S; P.Sv = Sv;
+  P.NA = na; P.NB = nb; P.N = na + nb;
+  const bool kv = Sv != nullptr;
+  const bool vload = tile_aligned16(A) && tile_aligned16(B) &&
+                     (!kv || (tile_aligned16(Av) && tile_aligned16(Bv)));
+  return launch_tiles_any<K, kTileSingle, kTileHeader>(cfg, P, vload, s);
+}
+
+template <typename K>
+hipError_t launch_merge_tiles_split(TileCfg cfg, const K *A, int64_t na, const K *B, int64_t nb,
+                                    K *S, const int64_t *a_split, hipStream_t s) {
+  TileArgs<K> P{};
+  P.A = A; P.B = B; P.S = S;
+  P.NA = na; P.NB = nb; P.N = na + nb;
+  P.a_split = a_split;
+  const bool vload = tile_aligned16(A) && tile_aligned16(B);
+  return launch_tiles_any<K, kTileSingle, kTileSplitArray>(cfg, P, vload, s);
+}
+
+template <typename K>
+hipError_t launch_sort_round_tiles(TileCfg cfg, const K *X, const uint32_t *Xv, K *Y,
+                                   uint32_t *Yv, int64_t n, int lw, hipStream_t s) {
+  TileArgs<K> P{};
+  P.A = X; P.B = X; P.Av = Xv; P.Bv = Xv; P.S = Y; P.Sv = Yv;
+  P.NA = n; P.NB = n; P.N = n;
+  P.lw = lw;
+  const bool kv = Yv != nullptr;
+  const bool vload = tile_aligned16(X) && (!kv || tile_aligned16(Xv));
+  return launch_tiles_any<K, kTileRuns, kTileHeader>(cfg, P, vload, s);
+}
+
+}  // namespace mp
+
+#define MP_TILE_INSTANTIATE(K)                                                               \
+  namespace mp {                                                                             \
+  template hipError_t launch_merge_tiles<K>(TileCfg, const K *, const uint32_t *, int64_t,   \
+                                            const K *, const uint32_t *, int64_t, K *,       \
+                                            uint32_t *, hipStream_t);                        \
+  template hipError_t launch_merge_tiles_split<K>(TileCfg, const K *, int64_t, const K *,    \
+                                                  int64_t, K *, const int64_t *,             \
+                                                  hipStream_t);                              \
+  template hipError_t launch_sort_round_tiles<K>(TileCfg, const K *, const uint32_t *, K *,  \
+                                                 uint32_t *, int64_t, int, hipStream_t);     \
+  }

@@ -157,7 +157,16 @@ def test_config_errors(L):
         mp.set_config("batched", 1)
     with pytest.raises(mp.MergePathError):
         mp.set_config("sort", 2, 256, 12)
+    with pytest.raises(mp.MergePathError):
+        mp.set_config("sort", 1, 512, 12)     # per-tile sort tiles are powers of two
+    with pytest.raises(mp.MergePathError):
+        mp.set_config("merge", 2, 0, 0)       # only per-tile mode picks its own tile
+    mp.set_config("merge", 1, 0, 0)           # per-tile, tile picked per call
+    assert mp.get_config("merge")[:3] == (1, 0, 0)
     mp.set_config("merge", None)
+    mp.set_config("sort", None)
+    assert mp.get_config("merge")[0] == 1 and mp.get_config("sort")[0] == 1
+    assert mp.get_config("batched")[0] == 2
 
 
 def test_partition_lanes_argument_errors(L):

@@ -91,7 +91,7 @@ def test_autotune_merge_and_cache(mp, orc, tmp_path):
     dA, dB = dev(A), dev(B)
     out = torch.empty(len(A) + len(B), dtype=torch.uint32, device="cuda")
     cfg = autotune.tune_merge(dA, dB, out, reps=3)
-    assert cfg[0] == 2 and mp.get_config("merge") == cfg
+    assert cfg[0] in (1, 2) and cfg[1] > 0 and mp.get_config("merge") == cfg
     got = host(mp.merge(dA, dB))
     assert got.tobytes() == orc.merge(A, B).tobytes()
     path = str(tmp_path / "tuned.json")

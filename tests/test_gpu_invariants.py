@@ -70,49 +70,75 @@ def _torch_dtype(np_dtype):
     return NP_TO_TORCH[np.dtype(np_dtype)]
 
 
-def _multi_tile_merge(mp, orc, A, B, min_tiles_per_group=4):
-    """Default-configuration merge of (A, B) into a guarded output, twice,
-    with different fills; returns nothing, asserts everything."""
+# The built-in merge (per tile: split search on the tile diagonals, then one
+# workgroup per tile) and the persistent kernel in its own default shapes
+# (192 x 24; 256 x 12 for 8-byte keys with values), whose workgroups walk
+# runs of tiles.
+PATHS = {"per_tile": None, "persistent": (2, 192, 24, 0, 0)}
+
+
+def _use(mp, path, kv8=False):
+    cfg = PATHS[path]
+    if cfg is not None and kv8:
+        cfg = (2, 256, 12, 0, 0)
+    if cfg is None:
+        mp.set_config("merge", None)
+    else:
+        mp.set_config("merge", *cfg)
+
+
+def _multi_tile_merge(mp, orc, A, B, path, min_tiles_per_group=4):
+    """Merge of (A, B) into a guarded output, twice, with different fills;
+    asserts everything."""
     from gpu_util import dev, first_mismatch
     want = orc.merge(A, B)
     dA, dB = dev(A), dev(B)
     out = Guarded(len(A) + len(B), _torch_dtype(A.dtype), FILLS[0])
-    for fill in FILLS:
-        out.refill(fill)
-        mp.timing_enable(True)
-        mp.merge(dA, dB, out=out.view)
-        tiles, _ = mp.stats_query()
-        groups = mp.stats_workgroups()
-        mp.timing_enable(False)
-        assert out.guards_intact(), "a store landed outside S"
-        assert first_mismatch(out.host(), want) is None, (A.dtype, len(A), len(B), fill)
-        assert groups > 0 and tiles >= min_tiles_per_group * groups, (tiles, groups)
+    _use(mp, path)
+    try:
+        for fill in FILLS:
+            out.refill(fill)
+            mp.timing_enable(True)
+            mp.merge(dA, dB, out=out.view)
+            tiles, _ = mp.stats_query()
+            groups = mp.stats_workgroups()
+            mp.timing_enable(False)
+            assert out.guards_intact(), "a store landed outside S"
+            assert first_mismatch(out.host(), want) is None, (A.dtype, len(A), len(B), fill)
+            if path == "persistent":
+                assert groups > 0 and tiles >= min_tiles_per_group * groups, (tiles, groups)
+    finally:
+        mp.set_config("merge", None)
 
 
-def test_default_merge_u32_uniform_many_tiles_per_group(mp, orc):
+@pytest.mark.parametrize("path", list(PATHS))
+def test_merge_u32_uniform_many_tiles(mp, orc, path):
     A, B = gen.uniform_pair(1 << 24, (1 << 24) + 4321, 101)
-    _multi_tile_merge(mp, orc, A, B)
+    _multi_tile_merge(mp, orc, A, B, path)
 
 
-def test_default_merge_u32_dups_many_tiles_per_group(mp, orc):
+@pytest.mark.parametrize("path", list(PATHS))
+def test_merge_u32_dups_many_tiles(mp, orc, path):
     A, B = gen.dups_pair(1 << 23, (1 << 23) - 999, 102, hi=1024)
-    _multi_tile_merge(mp, orc, A, B, min_tiles_per_group=2)
+    _multi_tile_merge(mp, orc, A, B, path, min_tiles_per_group=2)
 
 
-def test_default_merge_f32_mixture_many_tiles_per_group(mp, orc):
+@pytest.mark.parametrize("path", list(PATHS))
+def test_merge_f32_mixture_many_tiles(mp, orc, path):
     A, B = gen.f32_mixture_pair(1 << 23, (1 << 23) + 77, 103)
-    _multi_tile_merge(mp, orc, A, B, min_tiles_per_group=2)
+    _multi_tile_merge(mp, orc, A, B, path, min_tiles_per_group=2)
 
 
-def test_default_merge_u64_many_tiles_per_group(mp, orc):
+@pytest.mark.parametrize("path", list(PATHS))
+def test_merge_u64_many_tiles(mp, orc, path):
     A, B = gen.uniform_pair(1 << 23, (1 << 23) + 5, 104, gen.U64)
-    _multi_tile_merge(mp, orc, A, B, min_tiles_per_group=2)
+    _multi_tile_merge(mp, orc, A, B, path, min_tiles_per_group=2)
 
 
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("dt,log2n", [(gen.U32, 23), (gen.U64, 22)])
-def test_default_merge_kv_many_tiles_per_group(mp, orc, dt, log2n):
-    """Key-value merges in the default configuration (8-byte keys take their
-    own built-in tile), values = index in A ++ B, so stability is checked."""
+def test_merge_kv_many_tiles(mp, orc, dt, log2n, path):
+    """Key-value merges, values = index in A ++ B, so stability is checked."""
     from gpu_util import dev, first_mismatch
     n = 1 << log2n
     A, B = gen.uniform_pair(n, n + 1234, 105, dt)
@@ -122,39 +148,56 @@ def test_default_merge_kv_many_tiles_per_group(mp, orc, dt, log2n):
     m = len(A) + len(B)
     ok = Guarded(m, _torch_dtype(A.dtype), FILLS[0])
     ov = Guarded(m, _torch_dtype(np.uint32), FILLS[0])
-    for fill in FILLS:
-        ok.refill(fill)
-        ov.refill(fill)
-        mp.timing_enable(True)
-        mp.merge_kv(dA, dva, dB, dvb, out_k=ok.view, out_v=ov.view)
-        tiles, _ = mp.stats_query()
-        groups = mp.stats_workgroups()
-        mp.timing_enable(False)
-        assert ok.guards_intact() and ov.guards_intact()
-        assert first_mismatch(ok.host(), wk) is None
-        assert first_mismatch(ov.host(), wv) is None
-        assert groups > 0 and tiles >= 2 * groups, (tiles, groups)
+    _use(mp, path, kv8=dt == gen.U64)
+    try:
+        for fill in FILLS:
+            ok.refill(fill)
+            ov.refill(fill)
+            mp.timing_enable(True)
+            mp.merge_kv(dA, dva, dB, dvb, out_k=ok.view, out_v=ov.view)
+            tiles, _ = mp.stats_query()
+            groups = mp.stats_workgroups()
+            mp.timing_enable(False)
+            assert ok.guards_intact() and ov.guards_intact()
+            assert first_mismatch(ok.host(), wk) is None
+            assert first_mismatch(ov.host(), wv) is None
+            if path == "persistent":
+                assert groups > 0 and tiles >= 2 * groups, (tiles, groups)
+    finally:
+        mp.set_config("merge", None)
 
 
-def test_per_tile_mode_guards(mp, orc):
-    """The per-tile merge (mode 1: each workgroup searches its own two
-    splits) over many tiles, keys and key-value."""
+@pytest.mark.parametrize("shape", [(1024, 16), (1024, 8), (512, 16), (512, 12), (256, 16),
+                                   (256, 15), (256, 8), (128, 16)])
+def test_per_tile_shapes_guards(mp, orc, shape):
+    """Every per-tile shape (mode 1) over many tiles, keys and key-value,
+    4- and 8-byte keys; shapes whose LDS is not built for a key type report
+    MP_ERR_UNSUPPORTED."""
     from gpu_util import dev, first_mismatch
-    A, B = gen.uniform_pair(3_000_017, 2_500_001, 106)
-    va, vb = gen.index_payload(len(A), len(B))
-    wk, wv = orc.merge_kv(A, va, B, vb)
-    dA, dB, dva, dvb = dev(A), dev(B), dev(va), dev(vb)
-    m = len(A) + len(B)
-    for nt, vt in ((256, 16), (256, 8), (128, 16), (256, 15)):
+    nt, vt = shape
+    for dt in (gen.U32, gen.U64):
+        A, B = gen.uniform_pair(3_000_017, 2_500_001, 106, dt)
+        va, vb = gen.index_payload(len(A), len(B))
+        wk, wv = orc.merge_kv(A, va, B, vb)
+        dA, dB, dva, dvb = dev(A), dev(B), dev(va), dev(vb)
+        m = len(A) + len(B)
         mp.set_config("merge", 1, nt, vt)
         try:
-            out = Guarded(m, _torch_dtype(np.uint32), FILLS[0])
+            out = Guarded(m, _torch_dtype(A.dtype), FILLS[0])
             ov = Guarded(m, _torch_dtype(np.uint32), FILLS[1])
-            mp.merge(dA, dB, out=out.view)
+            try:
+                mp.merge(dA, dB, out=out.view)
+            except mp.MergePathError as e:
+                assert "UNSUPPORTED" in str(e) and dt == gen.U64 and nt * vt > 8192
+                continue
             assert out.guards_intact()
-            assert first_mismatch(out.host(), wk) is None, (nt, vt)
+            assert first_mismatch(out.host(), wk) is None, (nt, vt, dt)
             out.refill(FILLS[1])
-            mp.merge_kv(dA, dva, dB, dvb, out_k=out.view, out_v=ov.view)
+            try:
+                mp.merge_kv(dA, dva, dB, dvb, out_k=out.view, out_v=ov.view)
+            except mp.MergePathError as e:
+                assert "UNSUPPORTED" in str(e) and nt * vt * (A.itemsize + 4) > 64 * 1024
+                continue
             assert out.guards_intact() and ov.guards_intact()
             assert first_mismatch(out.host(), wk) is None
             assert first_mismatch(ov.host(), wv) is None
