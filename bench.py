@@ -2,8 +2,9 @@
 
 Headline: merge of two sorted uint32 arrays, |A| = |B| = 2^28, keys uniform
 in [0, 2^32) (seed 11), inputs resident in HBM, output preallocated.  One
-step = one mp_merge call (one persistent kernel: per-workgroup split search,
-LDS windows, per-lane split search, serial merge, coalesced stores).
+step = one mp_merge call (Algorithm 1: the split search on every tile
+diagonal, then one workgroup per 16384-key tile: LDS windows, per-lane split
+search, serial merge, coalesced stores).
 
 Prints ONE JSON line: throughput (Gkeys/s merged), the roofline of the merge
 kernel timed with HIP events that the library records on its launch stream,
@@ -33,9 +34,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gkeys/s merged & % HBM peak (2^28+2^28 u32); learned vs bsearch split time"
 LEGS = ("headline", "small", "kv", "sort", "batched", "learned", "setops")
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "merge_stream_u32_2p28.md")
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "merge_tile_u32_2p28.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1406_2628_amd", "csrc", f)
-                  for f in ("mp_stream_impl.h", "mp_device.h")]
+                  for f in ("mp_tile_impl.h", "mp_device.h")]
 
 
 def log(msg):
@@ -158,16 +159,38 @@ def leg_headline(args, out):
     step = lambda: mp.merge(dA, dB, out=dS)  # noqa: E731
     mp.timing_enable(False)
     ms = time_steps(step, args.steps, args.warmup)
+    # the same steps one by one, each between its own pair of events
+    per = event_times(step, max(20, args.steps), 0)
     # kernel durations over a second timed region: HIP events the library
-    # records on the launch stream around each kernel
+    # records on the launch stream around each kernel (split search on the
+    # tile diagonals, then the tile merge)
     mp.timing_enable(True)
     time_steps(step, args.steps, 0)
-    k_ms, k_n = mp.timing_query("merge_stream")
-    tiles, reloads = mp.stats_query()
+    k_ms, k_n = mp.timing_query("tile_merge")
+    s_ms, s_n = mp.timing_query("tile_splits")
     mp.timing_enable(False)
     kern_ms = k_ms / max(1, k_n)
+    splits_ms = s_ms / max(1, s_n)
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic = profiled_traffic()
+    # the split search alone on the same diagonals (Algorithm 2 only)
+    T = 1 << 14
+    tdiag = torch.clamp(torch.arange(n_out // T + 2, device="cuda", dtype=torch.int64) * T,
+                        max=n_out)
+    sp = torch.empty_like(tdiag)
+    part_ms = event_times(lambda: mp.partition(dA, dB, tdiag, out=sp), 20, 3)["median"]
+    del tdiag, sp
+    # measured copy of the same bytes (2^29 keys read, 2^29 written) with the
+    # bandwidth probe's best measured launch shape
+    log("bench: headline: copy reference")
+    cpy_src = torch.ones(n_out, dtype=torch.int32, device="cuda")
+    cpy_dst = torch.empty_like(cpy_src)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    cpy = event_times(lambda: mp.bw_probe("copy", cpy_src, cpy_dst, n_out * 4, 4, 64 * cus),
+                      20, 3)
+    del cpy_src, cpy_dst
+    copy_gbs = alg_bytes / (cpy["median"] * 1e-3) / 1e9
+    step_gbs = alg_bytes / (ms * 1e-3) / 1e9
 
     out.update({
         "metric": METRIC,
@@ -184,14 +207,20 @@ def leg_headline(args, out):
         "data": "synthetic (seeded uniform u32 keys, sorted)",
         "config": {"workload": f"merge of sorted u32 arrays, 2^{args.log2n}+2^{args.log2n} "
                                f"uniform keys, seed {seed}", "na": na, "nb": nb},
-        "hbm_frac_step": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": {"bound": "hbm", "kernel": "merge_pairs_kernel (single pair)",
+        "step_ms": {"median": round(per["median"], 4), "min": round(per["min"], 4),
+                    "mean": round(per["mean"], 4), "steps": max(20, args.steps)},
+        "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
+        "copy_reference": {"GBs_median": round(copy_gbs, 1),
+                           "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
+                           "step_frac_of_copy": round(step_gbs / copy_gbs, 4),
+                           "kernel_frac_of_copy": round(achieved / copy_gbs, 4)},
+        "partition_alone_ms": round(part_ms, 4),
+        "roofline": {"bound": "hbm", "kernel": "merge_tile_kernel (1024 x 16, single pair)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / 1e9, 4),
                      "traffic_unit": "GB per launch", "algorithmic_GB": round(alg_bytes / 1e9, 4),
-                     "kernel_ms": round(kern_ms, 4),
-                     "window_reload_rate": round(reloads / max(1, tiles), 6)},
+                     "kernel_ms": round(kern_ms, 4), "splits_kernel_ms": round(splits_ms, 4)},
     })
     # The same merge kept in registers (nothing stored; section 6's runs
     # that write to a local register): reading and comparing alone.
@@ -464,6 +493,22 @@ def leg_learned(args, ex):
     # probes of a lower-bound search over a window, averaged over buckets
     res["mean_window_probes"] = round(float(np.mean(np.ceil(np.log2(span + 1.0)))), 2)
     res["plain_probes"] = int(np.ceil(np.log2(n + 1.0)))
+    # The same method without the network: a zero-weight model (the
+    # proportional prior d * na / N alone) calibrated on the same pair and
+    # diagonals, so it gets its own per-bucket window table.
+    zero = mp.LearnedPartitioner(32, 5, 7)
+    zero.set_params(np.zeros(zero.num_params, np.float32))
+    zero_err = zero.calibrate(A, B, 1 << 20)
+    wz = zero.windows()
+    zspan = wz[:, 1] - wz[:, 0]
+    res["no_network"] = {
+        "max_val_err": int(zero_err),
+        "window_span_median": int(np.median(zspan)), "window_span_max": int(zspan.max()),
+        "mean_window_probes": round(float(np.mean(np.ceil(np.log2(zspan + 1.0)))), 2),
+        # one symmetric window from the largest error, no per-bucket table:
+        # probes of a search over 2 * err + 1 candidates, network vs prior
+        "symmetric_window_probes": int(np.ceil(np.log2(2 * zero_err + 1.0))),
+        "symmetric_window_probes_trained": int(np.ceil(np.log2(2 * res["max_val_err"] + 1.0)))}
     del A, B
     torch.cuda.empty_cache()
     log("bench: learned: timing on the evaluation pair (seed 60)")
@@ -476,15 +521,28 @@ def leg_learned(args, ex):
         out_p = torch.empty(P + 1, dtype=torch.int64, device="cuda")
         out_l = torch.empty(P + 1, dtype=torch.int64, device="cuda")
         fb = torch.zeros(1, dtype=torch.uint64, device="cuda")
+        out_z = torch.empty(P + 1, dtype=torch.int64, device="cuda")
         t_plain = time_steps(lambda: mp.partition(A, B, diag, out=out_p), 10, 3)
         t_learn = time_steps(lambda: lp.partition(A, B, diag, out=out_l), 10, 3)
+        t_zero = time_steps(lambda: zero.partition(A, B, diag, out=out_z), 10, 3)
         fb.zero_()
         lp.partition(A, B, diag, out=out_l, fallbacks=fb)
+        fbz = torch.zeros(1, dtype=torch.uint64, device="cuda")
+        zero.partition(A, B, diag, out=out_z, fallbacks=fbz)
         same = bool(torch.equal(out_p, out_l))
         sweep[f"P=2^{logp}"] = {"plain_ms": round(t_plain, 4), "learned_ms": round(t_learn, 4),
                                 "speedup": round(t_plain / t_learn, 3), "identical": same,
-                                "fallbacks": int(fb.cpu().numpy()[0])}
+                                "fallbacks": int(fb.cpu().numpy()[0]),
+                                "no_network_ms": round(t_zero, 4),
+                                "no_network_identical": bool(torch.equal(out_p, out_z)),
+                                "no_network_fallbacks": int(fbz.cpu().numpy()[0])}
     res["sweep"] = sweep
+    # training break-even: P = 2^18 partition calls whose saving repays the
+    # training time
+    s18 = sweep["P=2^18"]
+    gain_ms = s18["plain_ms"] - s18["learned_ms"]
+    res["training_break_even_calls_2p18"] = (round(res["train_s"] * 1e3 / gain_ms)
+                                             if gain_ms > 0 else None)
     # spot-check against the oracle on sampled diagonals (one sequential walk)
     Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
     ds = np.sort(np.random.default_rng(0).integers(0, N + 1, 256)).astype(np.int64)
@@ -544,7 +602,8 @@ def main():
         return
     legs = [x for x in args.legs.split(",") if x]
     out = {}
-    leg_headline(args, out)
+    if "headline" in legs:
+        leg_headline(args, out)
     ex = {}
     for name, fn in (("small", leg_small), ("kv", leg_kv), ("sort", leg_sort),
                      ("batched", leg_batched), ("learned", leg_learned), ("setops", leg_setops)):

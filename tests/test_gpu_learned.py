@@ -126,6 +126,52 @@ def test_training_reduces_loss(trained):
     assert lp.window == np.abs(w).max() and lp.window >= err
 
 
+def _mean_window_probes(lp):
+    w = lp.windows()
+    return float(np.mean(np.ceil(np.log2(w[:, 1] - w[:, 0] + 1.0))))
+
+
+def test_network_gain_attribution(mp, orc, trained):
+    """What the trained network adds, measured against the same method
+    without it: a zero-weight model (the proportional prior d * na / N
+    alone) calibrated on the same held-out pair and diagonals.
+
+    - One symmetric window (the largest calibration error on either side,
+      no per-bucket table): the network shrinks the largest error, so the
+      window search needs fewer probes than with the prior alone, and both
+      need fewer than the plain search.
+    - Per-bucket windows (the shipped calibration): the 16384-entry window
+      table already follows the split curve piecewise, and the network
+      adds no more than about one probe either way; both beat the plain
+      search by several probes.
+    Every variant gives the plain search's splits."""
+    lp, _, _, err, n = trained
+    from gpu_util import dev
+    A, B = map(dev, gen.f32_mixture_pair(n, n, 59))
+    z = mp.LearnedPartitioner(H, F, 11)           # same seed: same calibration diagonals
+    z.set_params(np.zeros(z.num_params, np.float32))
+    err_z = z.calibrate(A, B, CAL_DIAG)
+    plain = int(np.ceil(np.log2(n + 1)))
+    t_tab, z_tab = _mean_window_probes(lp), _mean_window_probes(z)
+    assert t_tab < plain - 4 and z_tab < plain - 4, (t_tab, z_tab, plain)
+    assert t_tab <= z_tab + 1.0, (t_tab, z_tab)
+    # symmetric windows: probes of a search over 2 * err + 1 candidates
+    assert err < err_z, (err, err_z)
+    assert np.ceil(np.log2(2 * err + 1)) < np.ceil(np.log2(2 * err_z + 1)) <= plain
+    E, Bv = gen.f32_mixture_pair(n, n, 60)
+    diag = np.random.default_rng(4).integers(0, 2 * n + 1, 20000).astype(np.int64)
+    _check_identical(mp, orc, z, E, Bv, diag)
+    saved = lp.windows()
+    lp.window = err + 1
+    z.window = err_z + 1
+    try:
+        _check_identical(mp, orc, lp, E, Bv, diag)
+        _check_identical(mp, orc, z, E, Bv, diag)
+    finally:
+        lp.calibrate(A, B, CAL_DIAG)                # restore the shipped windows
+    assert np.array_equal(lp.windows(), saved)
+
+
 def _calibration_windows_np(e, d, na, nb, n_diag):
     """The documented calibration rule, written out with a brute-force
     neighbourhood (the library uses running extremes)."""
