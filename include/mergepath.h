@@ -140,6 +140,24 @@ mp_status mp_set_op(int32_t op, mp_dtype kt, const void *A, int64_t na, const vo
                     void *stream);
 
 /*
+ * mp_set_op_noalloc -- mp_set_op for callers that cannot allocate device
+ * memory or pass a workspace (code under hipGraph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same operation, arguments and
+ * results as mp_set_op without ws / ws_bytes: the look-back state lives in a
+ * fixed scratch array of 4 MiB in device memory that the library owns, one
+ * per GPU, held until the process ends.  It allocates, frees and
+ * synchronises nothing.
+ *   na + nb  at most 1073731584 keys; larger inputs return
+ *            MP_ERR_UNSUPPORTED before anything is enqueued.
+ * Every call on one GPU shares that GPU's scratch (it is cleared by a kernel
+ * at the start of each call): calls that overlap in time on one GPU, from
+ * different streams or threads, race and give wrong counts and outputs.
+ * Serialise them (one stream, or events between streams).
+ */
+mp_status mp_set_op_noalloc(int32_t op, mp_dtype kt, const void *A, int64_t na, const void *B,
+                            int64_t nb, void *S, int64_t *count, void *stream);
+
+/*
  * mp_merge_split -- the second step of Algorithm 1 on splits the caller
  * already has: output tile k, S[k*tile, min((k+1)*tile, na+nb)), is merged
  * from the pair that a_split[k] and a_split[k+1] cut out (Corollary 6),

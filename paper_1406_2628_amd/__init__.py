@@ -54,6 +54,7 @@ def _declare(L):
         "mp_merge_split": ([i32, p, i64, p, i64, p, i32, p, p], i32),
         "mp_set_op_workspace_bytes": ([i64, i64], ctypes.c_size_t),
         "mp_set_op": ([i32, i32, p, i64, p, i64, p, p, p, ctypes.c_size_t, p], i32),
+        "mp_set_op_noalloc": ([i32, i32, p, i64, p, i64, p, p, p], i32),
         "mp_merge_kv": ([i32, i32, p, p, i64, p, p, i64, p, p, p], i32),
         "mp_merge_batched_workspace_bytes": ([i32, i64, i64], sz),
         "mp_merge_batched": ([i32, p, p, p, p, i64, i64, i64, p, p, sz, p], i32),
@@ -260,6 +261,18 @@ def set_op(op: str, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None =
     if k < 0:
         raise RuntimeError("mp_set_op: a tile's wait for the tiles before it gave up")
     return out[:k]
+
+
+def set_op_noalloc(op: str, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor,
+                   count: torch.Tensor):
+    """mp_set_op_noalloc: the set operation with the library's fixed device
+    scratch instead of a workspace.  ``out`` must hold the operation's room
+    and ``count`` is an int64 device scalar; nothing is allocated and
+    nothing synchronised.  Returns (out, count)."""
+    kt = _key_dtype(A, B)
+    _check(lib().mp_set_op_noalloc(SET_OPS[op], kt, _ptr(A), A.numel(), _ptr(B), B.numel(),
+                                   _ptr(out), _ptr(count), _stream(A.device)))
+    return out, count
 
 
 def merge_split(A: torch.Tensor, B: torch.Tensor, a_split: torch.Tensor, tile: int = 4096,

@@ -229,9 +229,9 @@ size_t mp_set_op_workspace_bytes(int64_t na, int64_t nb) {
   return (size_t)(3 * (setop_tiles(na + nb) + 1)) * sizeof(int64_t);
 }
 
-mp_status mp_set_op(int32_t op, mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb,
-                    void *S, int64_t *count, void *ws, size_t ws_bytes, void *stream) {
-  const char *fn = "mp_set_op";
+static mp_status set_op_common(const char *fn, int32_t op, mp_dtype kt, const void *A, int64_t na,
+                               const void *B, int64_t nb, void *S, int64_t *count, void *ws,
+                               size_t ws_bytes, bool noalloc, void *stream) {
   if (op < 0 || op > 3) return fail(MP_ERR_INVALID_ARG, "%s: op must be 0, 1, 2 or 3", fn);
   if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported key dtype %d", fn, (int)kt);
   const size_t es = dtype_size(kt);
@@ -245,24 +245,50 @@ mp_status mp_set_op(int32_t op, mp_dtype kt, const void *A, int64_t na, const vo
   const int64_t cap = (op == 0 || op == 2) ? na : na + nb;
   if ((st = check_array(S, cap, es, "S")) != MP_OK) return st;
   const size_t need = mp_set_op_workspace_bytes(na, nb);
-  if (!ws || ws_bytes < need)
-    return fail(MP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
-  if ((uintptr_t)ws % 8) return fail(MP_ERR_INVALID_ARG, "%s: workspace not 8-byte aligned", fn);
-  const Range rs = span(S, cap, es), rw = span(ws, (int64_t)need, 1), rc = span(count, 1, 8);
+  if (noalloc) {
+    if (need > (size_t)kSetScratchWords * sizeof(int64_t))
+      return fail(MP_ERR_UNSUPPORTED,
+                  "%s: na + nb = %lld exceeds the %lld keys the fixed scratch serves", fn,
+                  (long long)(na + nb), (long long)kSetScratchKeys);
+    ws = nullptr;  // set below from the device scratch
+  } else {
+    if (!ws || ws_bytes < need)
+      return fail(MP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+    if ((uintptr_t)ws % 8) return fail(MP_ERR_INVALID_ARG, "%s: workspace not 8-byte aligned", fn);
+  }
+  const Range rs = span(S, cap, es), rc = span(count, 1, 8);
   const Range ra = span(A, na, es), rb = span(B, nb, es);
+  const Range rw = noalloc ? Range{0, 0} : span(ws, (int64_t)need, 1);
   if (overlaps(rs, ra) || overlaps(rs, rb) || overlaps(rs, rw) || overlaps(rs, rc) ||
       overlaps(rw, ra) || overlaps(rw, rb) || overlaps(rw, rc) || overlaps(rc, ra) ||
       overlaps(rc, rb))
     return fail(MP_ERR_OVERLAP, "%s: S, count, workspace and the inputs must not overlap", fn);
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
+  if (noalloc) {
+    int64_t *p = nullptr;
+    e = setop_scratch_ptr(&p);
+    if (e != hipSuccess) return hip_fail(e, "mp_set_op_noalloc: scratch address");
+    ws = p;
+  }
   dispatch_key(kt, [&](auto k) {
     using K = decltype(k);
     KernelTimer timer("set_op", s);
     e = launch_set_op<K>(op, (const K *)A, na, (const K *)B, nb, (K *)S, cap, count,
                          (int64_t *)ws, s);
   });
-  return e == hipSuccess ? MP_OK : hip_fail(e, "mp_set_op launch");
+  return e == hipSuccess ? MP_OK : hip_fail(e, "set operation launch");
+}
+
+mp_status mp_set_op(int32_t op, mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb,
+                    void *S, int64_t *count, void *ws, size_t ws_bytes, void *stream) {
+  return set_op_common("mp_set_op", op, kt, A, na, B, nb, S, count, ws, ws_bytes, false, stream);
+}
+
+mp_status mp_set_op_noalloc(int32_t op, mp_dtype kt, const void *A, int64_t na, const void *B,
+                            int64_t nb, void *S, int64_t *count, void *stream) {
+  return set_op_common("mp_set_op_noalloc", op, kt, A, na, B, nb, S, count, nullptr, 0, true,
+                       stream);
 }
 
 mp_status mp_merge_split(mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb,

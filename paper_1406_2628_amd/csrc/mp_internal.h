@@ -104,6 +104,12 @@ hipError_t launch_merge_checksum(StreamCfg cfg, const K *A, int64_t na, const K 
 // + 1) int64 of device workspace (setop_tiles bounds the tile count of every
 // key type).
 int64_t setop_tiles(int64_t n);
+// The allocation-free variant's fixed scratch: kSetScratchWords int64 per
+// device (4 MiB), enough for na + nb up to kSetScratchKeys.
+constexpr int64_t kSetScratchWords = (int64_t)1 << 19;
+constexpr int64_t kSetScratchKeys = (kSetScratchWords / 3 - 1) * (512 * 12);
+// Device address of this device's scratch (looked up once per device).
+hipError_t setop_scratch_ptr(int64_t **out);
 template <typename K>
 hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb, K *S,
                          int64_t cap, int64_t *count, int64_t *ws, hipStream_t s);

@@ -28,7 +28,9 @@
 // counter), so every tile a workgroup waits on belongs to a workgroup that
 // is already running; each tile publishes its own count before it waits,
 // so every wait ends, and a bound on the polls backs that up.
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "mp_device.h"
 #include "mp_internal.h"
@@ -326,6 +328,32 @@ __global__ void setop_init_kernel(unsigned long long *__restrict__ status, int64
 }
 
 int64_t setop_tiles(int64_t n) { return (n + kSetTMin - 1) / kSetTMin; }
+
+// Fixed device scratch of the allocation-free entry point (mp_set_op_noalloc):
+// the splits, tile status words and ticket counter of one call, sized for
+// na + nb up to kSetScratchKeys.  Each GPU the library runs on holds its own
+// copy until the process ends.  In host code `scratch` names a host-side
+// stand-in; its device address comes from hipGetSymbolAddress, once per
+// device, and only that address is ever passed to a kernel.
+static __device__ __align__(256) int64_t scratch[kSetScratchWords];
+
+hipError_t setop_scratch_ptr(int64_t **out) {
+  static std::mutex mu;
+  static std::vector<int64_t *> per_device;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)per_device.size() <= dev) per_device.resize(dev + 1, nullptr);
+  if (!per_device[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    per_device[dev] = (int64_t *)p;
+  }
+  *out = per_device[dev];
+  return hipSuccess;
+}
 
 template <typename K>
 hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb, K *S,

@@ -80,6 +80,19 @@ def test_set_op_argument_errors(L):
     assert L.mp_set_op(0, MP_U32, a, 10, b, 10, s, c, P(0x40000), need, None) == OVERLAP
 
 
+def test_set_op_noalloc_argument_errors(L):
+    a, b, s, c = P(0x10000), P(0x20000), P(0x30000), P(0x40000)
+    assert L.mp_set_op_noalloc(4, MP_U32, a, 10, b, 10, s, c, None) == INVALID
+    assert L.mp_set_op_noalloc(0, 0, a, 10, b, 10, s, c, None) == UNSUPPORTED
+    assert L.mp_set_op_noalloc(0, MP_U32, a, 10, b, 10, s, None, None) == INVALID
+    assert L.mp_set_op_noalloc(0, MP_U32, a, 10, b, 10, P(0x10000 + 4), c, None) == OVERLAP
+    # inputs beyond the fixed scratch are refused before any device access
+    big = 1 << 30
+    assert L.mp_set_op_noalloc(1, MP_U32, P(0x10000), big, P(0x10000 + 8 * big), big,
+                               P(0x10000 + 16 * big), c, None) == UNSUPPORTED
+    assert b"scratch" in L.mp_last_error()
+
+
 def test_merge_split_argument_errors(L):
     a, b, sp, s = P(0x10000), P(0x20000), P(0x30000), P(0x40000)
     assert L.mp_merge_split(MP_U32, a, 10, b, 10, sp, 1000, s, None) == UNSUPPORTED
