@@ -57,9 +57,14 @@ enum Op { kOpMerge = 0, kOpBatched = 1, kOpSort = 2, kNumOps = 3 };
 // = 0), batches persistent.
 const mp_config kDefaultConfig[kNumOps] = {
     {1, 0, 0, 0, 0},     // merge
-    {2, 256, 16, 0, 0},  // batched
+    {1, 0, 0, 0, 0},     // batched
     {1, 0, 0, 0, 0},     // sort rounds
 };
+// Batches whose mean pair is shorter than this many keys stay on the
+// persistent kernel in the built-in configuration: per-pair tiles would
+// leave most lanes of each tile idle.
+constexpr int64_t kBatchTileMinMeanPair = 1024;
+const mp_config kBatchedPersistent = {2, 256, 16, 0, 0};
 // The persistent shape the no-store diagnostic uses when the merge is not
 // set to a persistent shape that has a no-store variant.
 const mp_config kChecksumConfig = {2, 192, 24, 0, 0};
@@ -381,8 +386,10 @@ mp_status mp_set_config(const char *op, const mp_config *cfg) {
   if ((cfg->mode != 1 && cfg->mode != 2) || cfg->grid < 0 ||
       (!auto_tile && (cfg->nt <= 0 || cfg->vt <= 0)))
     return fail(MP_ERR_INVALID_ARG, "mp_set_config: invalid configuration");
-  if (cfg->mode == 1 && i == kOpBatched)
-    return fail(MP_ERR_UNSUPPORTED, "mp_set_config: per-tile mode exists for merge and sort only");
+  if (cfg->mode == 1 && i == kOpBatched && !auto_tile &&
+      (int64_t)cfg->nt * cfg->vt < kBatchMinTile)
+    return fail(MP_ERR_UNSUPPORTED, "mp_set_config: per-tile batches need tiles of at least %lld",
+                (long long)kBatchMinTile);
   if (i == kOpSort && !auto_tile) {
     // merge rounds rely on tiles that divide every run pair (2w >= 2 blocks;
     // persistent rounds as built assume the smallest block of 4096)
@@ -435,15 +442,15 @@ mp_status mp_bw_probe(int32_t kind, const void *src, void *dst, int64_t n_bytes,
 }
 
 size_t mp_merge_batched_workspace_bytes(mp_dtype kt, int64_t n_pairs, int64_t total) {
-  (void)kt; (void)n_pairs; (void)total;
-  return 0;  // the persistent kernel keeps its pair offsets in LDS
+  (void)kt;
+  if (n_pairs < 0 || total < 0) return 0;
+  return (size_t)batch_tile_ws_bytes(n_pairs, total);
 }
 
 mp_status mp_merge_batched(mp_dtype kt, const void *A, const int64_t *a_off,
                            const void *B, const int64_t *b_off, int64_t n_pairs,
                            int64_t total_a, int64_t total_b, void *S, void *ws,
                            size_t ws_bytes, void *stream) {
-  (void)ws; (void)ws_bytes;
   const char *fn = "mp_merge_batched";
   if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported key dtype %d", fn, (int)kt);
   if (n_pairs < 0) return fail(MP_ERR_INVALID_ARG, "%s: negative pair count", fn);
@@ -463,21 +470,47 @@ mp_status mp_merge_batched(mp_dtype kt, const void *A, const int64_t *a_off,
       overlaps(rs, span(a_off, n_pairs + 1, 8)) || overlaps(rs, span(b_off, n_pairs + 1, 8)))
     return fail(MP_ERR_OVERLAP, "%s: output overlaps an input", fn);
   if (n == 0) return MP_OK;
-  const mp_config cfg = current_config(kOpBatched);
+  mp_config cfg = current_config(kOpBatched);
+  TileCfg tc{cfg.nt, cfg.vt};
+  // per-pair tiles index pairs with 32-bit integers and launch one
+  // workgroup per possible tile
+  const bool tiles_fit = n_pairs < ((int64_t)1 << 30) && n / kBatchMinTile + n_pairs < INT32_MAX;
+  if (cfg.mode == 1 && cfg.nt == 0) {
+    // built-in: 4096-key tiles per pair, or the persistent kernel for short pairs
+    if (n < kBatchTileMinMeanPair * n_pairs || !tiles_fit) cfg = kBatchedPersistent;
+    else tc = TileCfg{256, 16};
+  }
+  if (cfg.mode == 1 && !tiles_fit)
+    return fail(MP_ERR_UNSUPPORTED, "%s: per-pair tiles take fewer than 2^30 pairs", fn);
+  if (cfg.mode == 1) {
+    const size_t need = mp_merge_batched_workspace_bytes(kt, n_pairs, n);
+    if (!ws || ws_bytes < need)
+      return fail(MP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+    if ((uintptr_t)ws % 8) return fail(MP_ERR_INVALID_ARG, "%s: workspace not 8-byte aligned", fn);
+    const Range rw = span(ws, (int64_t)need, 1);
+    if (overlaps(rw, rs) || overlaps(rw, span(A, total_a, es)) || overlaps(rw, span(B, total_b, es)) ||
+        overlaps(rw, span(a_off, n_pairs + 1, 8)) || overlaps(rw, span(b_off, n_pairs + 1, 8)))
+      return fail(MP_ERR_OVERLAP, "%s: workspace overlaps an input or the output", fn);
+  }
   const StreamCfg sc{cfg.nt, cfg.vt, cfg.grid, cfg.margin};
   hipStream_t s = (hipStream_t)stream;
   const std::vector<uint64_t> key = {
       1, (uint64_t)kt, (uint64_t)(uintptr_t)A, (uint64_t)(uintptr_t)a_off,
       (uint64_t)(uintptr_t)B, (uint64_t)(uintptr_t)b_off, (uint64_t)n_pairs,
       (uint64_t)total_a, (uint64_t)total_b, (uint64_t)(uintptr_t)S,
-      (uint64_t)cfg.nt, (uint64_t)cfg.vt, (uint64_t)cfg.grid, (uint64_t)(uint32_t)cfg.margin};
+      (uint64_t)cfg.mode, (uint64_t)tc.nt, (uint64_t)tc.vt, (uint64_t)cfg.grid,
+      (uint64_t)(uint32_t)cfg.margin, (uint64_t)(uintptr_t)ws};
   hipError_t e = run_maybe_graph(key, s, [&](hipStream_t st) {
     hipError_t ee = hipSuccess;
     dispatch_key(kt, [&](auto k) {
       using K = decltype(k);
       KernelTimer timer("merge_batched", st);
-      ee = launch_merge_batched<K>(sc, (const K *)A, a_off, (const K *)B, b_off, n_pairs,
-                                   total_a, total_b, (K *)S, st);
+      if (cfg.mode == 1)
+        ee = launch_merge_batched_tiles<K>(tc, (const K *)A, a_off, (const K *)B, b_off, n_pairs,
+                                           total_a, total_b, (K *)S, ws, st);
+      else
+        ee = launch_merge_batched<K>(sc, (const K *)A, a_off, (const K *)B, b_off, n_pairs,
+                                     total_a, total_b, (K *)S, st);
     });
     return ee;
   });
@@ -632,7 +665,7 @@ static mp_status autotune(Op op, int reps, hipStream_t s, Run run, Setup setup, 
     }
   };
   const int cus = device_cu_count();
-  if (op != kOpBatched) {
+  {
     for (const auto &shape : kTuneTileShapes) {
       const mp_config c{1, shape[0], shape[1], 0, 0};
       if (op == kOpSort) {
@@ -692,11 +725,24 @@ mp_status mp_autotune_batched(mp_dtype kt, const void *A, const int64_t *a_off, 
                               const int64_t *b_off, int64_t n_pairs, int64_t total_a,
                               int64_t total_b, void *S, int reps, mp_config *best, void *stream) {
   if (!best) return fail(MP_ERR_INVALID_ARG, "mp_autotune_batched: NULL result");
+  // the per-tile candidates need a workspace: one for the whole tuning run
+  // (a set-up call, not the merge itself)
+  const size_t need = mp_merge_batched_workspace_bytes(kt, n_pairs, total_a + total_b);
+  void *ws = nullptr;
+  if (need > 0) {
+    const hipError_t e = hipMalloc(&ws, need);
+    if (e != hipSuccess) return hip_fail(e, "mp_autotune_batched: workspace");
+  }
   auto run = [&]() {
-    return mp_merge_batched(kt, A, a_off, B, b_off, n_pairs, total_a, total_b, S, nullptr, 0,
+    return mp_merge_batched(kt, A, a_off, B, b_off, n_pairs, total_a, total_b, S, ws, need,
                             stream);
   };
-  return autotune(kOpBatched, reps, (hipStream_t)stream, run, [] {}, best);
+  const mp_status st = autotune(kOpBatched, reps, (hipStream_t)stream, run, [] {}, best);
+  if (ws) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    (void)hipFree(ws);
+  }
+  return st;
 }
 
 mp_status mp_autotune_sort(mp_dtype kt, mp_dtype vt, const void *keys_in, const void *vals_in,

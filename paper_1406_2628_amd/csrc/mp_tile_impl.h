@@ -22,7 +22,15 @@
 // Layouts: kSingle merges (A, B); kRuns is one round of merge sort over X:
 // pair k is (X[2wk, 2wk+w), X[2wk+w, 2wk+2w)) clipped to n, left run as A
 // (stable), and tiles (a power of two dividing 2w) never cross a pair end,
-// so every tile is again one plain pair of ranges of X.
+// so every tile is again one plain pair of ranges of X.  kExplicit is a
+// batch of independent pairs given by CSR offsets (Corollary 6 pair by
+// pair): each pair is cut into its own tiles of at most T outputs, tile j of
+// pair k writing S[out(k) + jT, ...) with out(k) = a_off(k) + b_off(k), so
+// again no tile crosses a pair end.  Their number is only known on the
+// device: a count-and-scan over the pairs builds the first tile of every
+// pair and the pair of every tile in the caller's workspace, and the
+// launches cover an upper bound (N / T + pairs), surplus workgroups exiting
+// at once.
 #pragma once
 
 #include "mp_device.h"
@@ -30,7 +38,7 @@
 
 namespace mp {
 
-enum TileKind { kTileSingle = 0, kTileRuns = 1 };
+enum TileKind { kTileSingle = 0, kTileRuns = 1, kTileExplicit = 2 };
 enum TileSrc { kTileHeader = 0, kTileSplitArray = 1 };
 
 template <typename K>
@@ -43,8 +51,112 @@ struct TileArgs {
   int64_t N;                // outputs (kTileSingle: NA + NB; kTileRuns: n)
   int lw;                   // kTileRuns: log2 of the run width
   const int64_t *a_split;   // kTileSplitArray: the caller's splits
-  int64_t n_tiles;
+  int64_t n_tiles;          // kTileExplicit: an upper bound of the tile count
+  // kTileExplicit
+  const int64_t *a_off, *b_off;  // CSR offsets of the pairs (n_pairs + 1)
+  int64_t n_pairs;
+  int64_t *tile_off;        // first tile of each pair (n_pairs + 1; workspace)
+  int32_t *tile_pair;       // pair of each tile (workspace)
+  int64_t *bsum;            // tile counts of blocks of pairs (workspace)
 };
+
+// Pair k of a batch with its offsets kept inside the arrays and
+// non-decreasing (no-ops for valid offsets): A[a0, a1) and B[b0, b1).
+template <typename K>
+__device__ __forceinline__ void batch_pair(const TileArgs<K> &P, int64_t k, int64_t &a0,
+                                           int64_t &a1, int64_t &b0, int64_t &b1) {
+  auto clamp = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  a0 = clamp(P.a_off[k], 0, P.NA);
+  a1 = clamp(P.a_off[k + 1], a0, P.NA);
+  b0 = clamp(P.b_off[k], 0, P.NB);
+  b1 = clamp(P.b_off[k + 1], b0, P.NB);
+}
+
+// ---- tiles of a batch: count, scan, fill ------------------------------------
+template <typename K>
+__device__ __forceinline__ int64_t batch_tiles(const TileArgs<K> &P, int64_t k, int64_t T) {
+  int64_t a0, a1, b0, b1;
+  batch_pair(P, k, a0, a1, b0, b1);
+  return ((a1 - a0) + (b1 - b0) + T - 1) / T;
+}
+
+// Inclusive scan of one value per lane across the workgroup; *total gets
+// the sum of all lanes.
+__device__ __forceinline__ int64_t batch_block_scan(int64_t v, int64_t *total) {
+  __shared__ int64_t s_w[kBatchLanes / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(v, o);
+    if (lane >= o) v += y;
+  }
+  if (lane == 63) s_w[wave] = v;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kBatchLanes / 64; ++w) {
+    const int64_t t = s_w[w];
+    before += w < wave ? t : 0;
+    all += t;
+  }
+  *total = all;
+  return v + before;
+}
+
+// Pass 1: tiles of each block of pairs.
+template <typename K>
+__global__ __launch_bounds__(kBatchLanes) void batch_count_kernel(TileArgs<K> P, int64_t T) {
+  const int64_t k0 = (int64_t)blockIdx.x * kBatchPairsPerBlock + (int64_t)threadIdx.x * kBatchPer;
+  int64_t c = 0;
+#pragma unroll
+  for (int i = 0; i < kBatchPer; ++i)
+    if (k0 + i < P.n_pairs) c += batch_tiles(P, k0 + i, T);
+  int64_t total;
+  batch_block_scan(c, &total);
+  if (threadIdx.x == 0) P.bsum[blockIdx.x] = total;
+}
+
+// Pass 2 (one workgroup): block counts to exclusive block offsets, in place.
+template <typename K>
+__global__ __launch_bounds__(kBatchLanes) void batch_sums_kernel(TileArgs<K> P, int64_t n_blocks) {
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < n_blocks; b0 += kBatchLanes) {
+    const int64_t b = b0 + threadIdx.x;
+    const int64_t v = b < n_blocks ? P.bsum[b] : 0;
+    int64_t total;
+    const int64_t incl = batch_block_scan(v, &total);
+    __syncthreads();  // every lane has read s_w before the next round writes it
+    if (b < n_blocks) P.bsum[b] = carry + incl - v;
+    carry += total;
+  }
+}
+
+// Pass 3: first tile of every pair (and the tile total), and the pair of
+// every tile.
+template <typename K>
+__global__ __launch_bounds__(kBatchLanes) void batch_fill_kernel(TileArgs<K> P, int64_t T) {
+  const int64_t k0 = (int64_t)blockIdx.x * kBatchPairsPerBlock + (int64_t)threadIdx.x * kBatchPer;
+  int64_t c[kBatchPer], sum = 0;
+#pragma unroll
+  for (int i = 0; i < kBatchPer; ++i) {
+    c[i] = k0 + i < P.n_pairs ? batch_tiles(P, k0 + i, T) : 0;
+    sum += c[i];
+  }
+  int64_t total;
+  int64_t t = batch_block_scan(sum, &total) - sum + P.bsum[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kBatchPer; ++i) {
+    const int64_t k = k0 + i;
+    if (k < P.n_pairs) {
+      P.tile_off[k] = t;
+      // (offsets that overlap across pairs could count more tiles than the
+      // launches cover; those are never launched and get no entry)
+      for (int64_t j = 0; j < c[i] && t + j < P.n_tiles; ++j) P.tile_pair[t + j] = (int32_t)k;
+      t += c[i];
+      if (k == P.n_pairs - 1) P.tile_off[P.n_pairs] = t;
+    }
+  }
+}
 
 // Header bytes at the start of each tile's range of S.
 constexpr int kTileHdrBytes = 32;
@@ -52,10 +164,16 @@ constexpr int kTileHdrBytes = 32;
 template <typename K>
 __device__ __forceinline__ void put_tile_hdr(K *S, int64_t d, int slot, int64_t a, int64_t b) {
   uint32_t *w = reinterpret_cast<uint32_t *>(S + d) + 4 * slot;
-  w[0] = (uint32_t)a;
-  w[1] = (uint32_t)((uint64_t)a >> 32);
-  w[2] = (uint32_t)b;
-  w[3] = (uint32_t)((uint64_t)b >> 32);
+  const u32x4 v = {(uint32_t)a, (uint32_t)((uint64_t)a >> 32), (uint32_t)b,
+                   (uint32_t)((uint64_t)b >> 32)};
+  if (((uintptr_t)w % 16) == 0) {
+    *reinterpret_cast<u32x4 *>(w) = v;  // one 16-byte store (S aligned)
+  } else {
+    w[0] = v.x;
+    w[1] = v.y;
+    w[2] = v.z;
+    w[3] = v.w;
+  }
 }
 
 template <typename K>
@@ -79,14 +197,39 @@ __device__ __forceinline__ void run_pair(int64_t d, int64_t n, int lw, int64_t &
 template <typename K, int KIND, int G>
 __global__ __launch_bounds__(256) void tile_splits_kernel(TileArgs<K> P, int64_t T) {
   const int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) / G;
-  if (k > P.n_tiles) return;  // a group exits as one (G divides 256)
-  const int64_t N = P.N;
-  const int64_t D = k * T < N ? k * T : N;
-  int64_t sa, sb, ea, eb;  // start of tile k, end of tile k - 1
   auto search = [&](int64_t d, int64_t lo, int64_t hi, auto ga, auto gb) -> int64_t {
     if constexpr (G == 1) return split_search<int64_t>(d, lo, hi, ga, gb);
     else return group_split_search<G, int64_t>(d, lo, hi, ga, gb);
   };
+  if constexpr (KIND == kTileExplicit) {
+    // k is a tile: its start inside its own pair, and the end of the tile
+    // before it in the same pair; the pair's last tile also gets the pair end
+    if (k >= P.tile_off[P.n_pairs]) return;  // a group exits as one
+    const int64_t pk = P.tile_pair[k], j = k - P.tile_off[pk];
+    int64_t a0, a1, b0, b1;
+    batch_pair(P, pk, a0, a1, b0, b1);
+    const int64_t size = (a1 - a0) + (b1 - b0), dl = j * T;
+    int64_t lo, hi;
+    diag_range<int64_t>(dl, a1 - a0, b1 - b0, lo, hi);
+    const K *A = P.A + a0, *B = P.B + b0;
+    const int64_t a = j == 0 ? 0 : search(dl, lo, hi, [&](int64_t i) { return A[i]; },
+                                          [&](int64_t q) { return B[q]; });
+    if constexpr (G > 1) {
+      if ((threadIdx.x & (G - 1)) != 0) return;
+    }
+    const int64_t out = a0 + b0;
+    const int64_t n = size - dl < T ? size - dl : T;
+    if (n * (int64_t)sizeof(K) >= kTileHdrBytes) {
+      put_tile_hdr(P.S, out + dl, 0, a0 + a, b0 + (dl - a));
+      if (dl + T >= size) put_tile_hdr(P.S, out + dl, 1, a1, b1);
+    }
+    if (j > 0) put_tile_hdr(P.S, out + dl - T, 1, a0 + a, b0 + (dl - a));  // full tile
+    return;
+  } else {
+  if (k > P.n_tiles) return;  // a group exits as one (G divides 256)
+  const int64_t N = P.N;
+  const int64_t D = k * T < N ? k * T : N;
+  int64_t sa, sb, ea, eb;  // start of tile k, end of tile k - 1
   if constexpr (KIND == kTileSingle) {
     int64_t lo, hi;
     diag_range<int64_t>(D, P.NA, P.NB, lo, hi);
@@ -128,6 +271,7 @@ __global__ __launch_bounds__(256) void tile_splits_kernel(TileArgs<K> P, int64_t
   }
   if (k < P.n_tiles && tile_bytes(P, T, k) >= kTileHdrBytes) put_tile_hdr(P.S, k * T, 0, sa, sb);
   if (k > 0 && tile_bytes(P, T, k - 1) >= kTileHdrBytes) put_tile_hdr(P.S, (k - 1) * T, 1, ea, eb);
+  }
 }
 
 // Chunk of CH elements at src + g: one vector access when the chunk lies
@@ -188,8 +332,31 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
   const int tid = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t N = P.N, NA = P.NA, NB = P.NB;
-  const int64_t d0 = tile * T;
-  const int n = (int)(N - d0 < T ? N - d0 : T);
+  // output range of the tile, and for a header-less tile the pair it ends
+  // ([alo, ia) of A and [blo, ib) of B)
+  int64_t d0;
+  int n;
+  int64_t alo = 0, blo = 0, ia = NA, ib = NB;
+  if constexpr (KIND == kTileExplicit) {
+    if (tile >= P.tile_off[P.n_pairs]) return;  // past the batch's tiles
+    const int64_t pk = P.tile_pair[tile], j = tile - P.tile_off[pk];
+    batch_pair(P, pk, alo, ia, blo, ib);
+    const int64_t rest = (ia - alo) + (ib - blo) - j * T;
+    d0 = alo + blo + j * T;
+    n = (int)(rest < T ? rest : T);
+    if (n <= 0) return;  // (only for inconsistent workspace contents)
+  } else {
+    d0 = tile * T;
+    n = (int)(N - d0 < T ? N - d0 : T);
+    if constexpr (KIND == kTileRuns) {
+      int64_t P0, aE, bE;
+      run_pair(d0, N, P.lw, P0, aE, bE);
+      alo = P0;
+      blo = aE;
+      ia = aE;
+      ib = bE;
+    }
+  }
 
   // ---- the tile's pair --------------------------------------------------
   int64_t a0, b0, a1;
@@ -208,18 +375,10 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
     b0 = (int64_t)(((uint64_t)h[3] << 32) | h[2]);
     a1 = (int64_t)(((uint64_t)h[5] << 32) | h[4]);
   } else {
-    // last tile, shorter than a header: from the end of the grid (or of its
-    // run pair) step the path back n times; each step takes the larger of
-    // the two keys before the cursor, B on ties (ties went to A forwards)
-    int64_t alo = 0, blo = 0, ia = NA, ib = NB;
-    if constexpr (KIND == kTileRuns) {
-      int64_t P0, aE, bE;
-      run_pair(d0, N, P.lw, P0, aE, bE);
-      alo = P0;
-      blo = aE;
-      ia = aE;
-      ib = bE;
-    }
+    // last tile (of the grid, run pair or batch pair), shorter than a
+    // header: from that end step the path back n times; each step takes the
+    // larger of the two keys before the cursor, B on ties (ties went to A
+    // forwards)
     a1 = ia;
     for (int s = 0; s < n; ++s) {
       const bool ta = ia > alo && (ib <= blo || P.B[ib - 1] < P.A[ia - 1]);
@@ -348,7 +507,8 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
 
 template <typename K, int KIND>
 static hipError_t launch_tile_splits(const TileArgs<K> &P, int64_t T, hipStream_t s) {
-  const int64_t n_b = P.n_tiles + 1;
+  // boundaries 0 .. n_tiles, or for a batch one item per (possible) tile
+  const int64_t n_b = KIND == kTileExplicit ? P.n_tiles : P.n_tiles + 1;
   const int g = partition_lanes(n_b);
   const int64_t blocks = (n_b * g + 255) / 256;
   switch (g) {
@@ -379,6 +539,21 @@ static hipError_t launch_tiles_shape(TileArgs<K> P, bool vload, hipStream_t s) {
     constexpr int64_t T = (int64_t)NT * VT;
     P.n_tiles = (P.N + T - 1) / T;
     if (P.n_tiles == 0) return hipSuccess;
+    if constexpr (KIND == kTileExplicit) {
+      // tiles per pair, scanned into the workspace
+      P.n_tiles += P.n_pairs;
+      const int64_t n_blocks = (P.n_pairs + kBatchPairsPerBlock - 1) / kBatchPairsPerBlock;
+      P.bsum = P.tile_off + (P.n_pairs + 1);
+      P.tile_pair = reinterpret_cast<int32_t *>(P.bsum + n_blocks);
+      KernelTimer timer("batch_tiles", s);
+      hipLaunchKernelGGL((batch_count_kernel<K>), dim3((unsigned)n_blocks), dim3(kBatchLanes), 0, s,
+                         P, T);
+      hipLaunchKernelGGL((batch_sums_kernel<K>), dim3(1), dim3(kBatchLanes), 0, s, P, n_blocks);
+      hipLaunchKernelGGL((batch_fill_kernel<K>), dim3((unsigned)n_blocks), dim3(kBatchLanes), 0, s,
+                         P, T);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     if constexpr (SRC == kTileHeader) {
       KernelTimer timer("tile_splits", s);
       const hipError_t e = launch_tile_splits<K, KIND>(P, T, s);
@@ -397,11 +572,12 @@ static hipError_t launch_tiles_shape(TileArgs<K> P, bool vload, hipStream_t s) {
 
 template <typename K, int KIND, int SRC>
 static hipError_t launch_tiles_any(TileCfg cfg, const TileArgs<K> &P, bool vload, hipStream_t s) {
-  // (merges on given splits carry keys only)
-  const bool kv = SRC == kTileHeader && P.Sv != nullptr;
+  // (merges on given splits and batches carry keys only)
+  constexpr bool KV_OK = SRC == kTileHeader && KIND != kTileExplicit;
+  const bool kv = KV_OK && P.Sv != nullptr;
 #define MP_TILE_CASE(NT_, VT_)                                                             \
   if (cfg.nt == NT_ && cfg.vt == VT_) {                                                    \
-    if constexpr (SRC == kTileHeader)                                                      \
+    if constexpr (KV_OK)                                                                   \
       if (kv) return launch_tiles_shape<K, true, NT_, VT_, KIND, SRC>(P, vload, s);        \
     return launch_tiles_shape<K, false, NT_, VT_, KIND, SRC>(P, vload, s);                 \
   }
@@ -444,6 +620,20 @@ hipError_t launch_merge_tiles_split(TileCfg cfg, const K *A, int64_t na, const K
 }
 
 template <typename K>
+hipError_t launch_merge_batched_tiles(TileCfg cfg, const K *A, const int64_t *a_off, const K *B,
+                                      const int64_t *b_off, int64_t n_pairs, int64_t total_a,
+                                      int64_t total_b, K *S, void *ws, hipStream_t s) {
+  if ((int64_t)cfg.nt * cfg.vt < kBatchMinTile) return hipErrorNotSupported;
+  TileArgs<K> P{};
+  P.A = A; P.B = B; P.S = S;
+  P.NA = total_a; P.NB = total_b; P.N = total_a + total_b;
+  P.a_off = a_off; P.b_off = b_off; P.n_pairs = n_pairs;
+  P.tile_off = reinterpret_cast<int64_t *>(ws);
+  const bool vload = tile_aligned16(A) && tile_aligned16(B);
+  return launch_tiles_any<K, kTileExplicit, kTileHeader>(cfg, P, vload, s);
+}
+
+template <typename K>
 hipError_t launch_sort_round_tiles(TileCfg cfg, const K *X, const uint32_t *Xv, K *Y,
                                    uint32_t *Yv, int64_t n, int lw, hipStream_t s) {
   TileArgs<K> P{};
@@ -467,4 +657,8 @@ hipError_t launch_sort_round_tiles(TileCfg cfg, const K *X, const uint32_t *Xv, 
                                                   hipStream_t);                              \
   template hipError_t launch_sort_round_tiles<K>(TileCfg, const K *, const uint32_t *, K *,  \
                                                  uint32_t *, int64_t, int, hipStream_t);     \
+  template hipError_t launch_merge_batched_tiles<K>(TileCfg, const K *, const int64_t *,     \
+                                                    const K *, const int64_t *, int64_t,     \
+                                                    int64_t, int64_t, K *, void *,           \
+                                                    hipStream_t);                            \
   }

@@ -158,6 +158,15 @@ def test_sort_and_batched_argument_errors(L):
     assert L.mp_merge_batched(MP_I32, a, None, b, bo, 3, 5, 5, s, None, 0, None) == INVALID
     assert L.mp_merge_batched(MP_I32, a, ao, b, bo, 3, 5, 5, P(0x10000 + 8), None, 0, None) == OVERLAP
     assert L.mp_merge_batched(MP_I32, None, None, None, None, 0, 0, 0, None, None, 0, None) == OK
+    # per-pair tiles (mean pair >= 1024 keys) need the workspace
+    a2, b2, s2, w2 = P(0x100000), P(0x200000), P(0x300000), P(0x400000)
+    need = L.mp_merge_batched_workspace_bytes(MP_I32, 1, 4000)
+    assert need > 0
+    assert L.mp_merge_batched(MP_I32, a2, ao, b2, bo, 1, 2000, 2000, s2, None, 0, None) == WORKSPACE
+    assert L.mp_merge_batched(MP_I32, a2, ao, b2, bo, 1, 2000, 2000, s2, w2, need - 8, None) == WORKSPACE
+    assert L.mp_merge_batched(MP_I32, a2, ao, b2, bo, 1, 2000, 2000, s2, P(0x400004), need, None) == INVALID
+    assert L.mp_merge_batched(MP_I32, a2, ao, b2, bo, 1, 2000, 2000, s2, P(0x300000 + 64), need,
+                              None) == OVERLAP
 
 
 def test_config_errors(L):
@@ -167,7 +176,9 @@ def test_config_errors(L):
     with pytest.raises(mp.MergePathError):
         mp.set_config("merge", 3)
     with pytest.raises(mp.MergePathError):
-        mp.set_config("batched", 1)
+        mp.set_config("batched", 1, 128, 8)   # per-tile batches need tiles of >= 2048 keys
+    mp.set_config("batched", 1, 256, 8)
+    mp.set_config("batched", None)
     with pytest.raises(mp.MergePathError):
         mp.set_config("sort", 2, 256, 12)
     with pytest.raises(mp.MergePathError):
@@ -179,7 +190,7 @@ def test_config_errors(L):
     mp.set_config("merge", None)
     mp.set_config("sort", None)
     assert mp.get_config("merge")[0] == 1 and mp.get_config("sort")[0] == 1
-    assert mp.get_config("batched")[0] == 2
+    assert mp.get_config("batched")[:3] == (1, 0, 0)
 
 
 def test_partition_lanes_argument_errors(L):

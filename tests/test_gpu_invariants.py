@@ -319,3 +319,69 @@ def test_set_op_unsorted_inputs_stay_inside_s(mp, op):
         k = int(host(count)[0])
         assert out.guards_intact() and cnt.guards_intact(), (op, len(A_), len(B_))
         assert 0 <= k <= cap, (k, cap)
+
+
+def _batch_edge_pairs(T, seed):
+    """Pair sizes that meet every edge of the per-pair tiles of T outputs:
+    empty pairs (runs of them), one-sided pairs, sizes just under, at and
+    just over multiples of T (last tiles of 1..7 keys, too short for a
+    header), and lognormal bulk."""
+    g = np.random.default_rng(seed)
+    sizes = [0, 0, 0, T, T - 1, T + 1, 2 * T, 2 * T + 3, 3 * T + 7, 1, 2, 7, 8, 9, 5 * T + 5]
+    sizes += list(np.clip(np.rint(g.lognormal(np.log(0.7 * T), 0.8, 300)), 0, 8 * T).astype(int))
+    sizes += [0] * 20 + [17 * T + 6]
+    na, nb = [], []
+    for i, s in enumerate(sizes):
+        if i % 7 == 3:
+            a = s          # B empty
+        elif i % 7 == 5:
+            a = 0          # A empty
+        else:
+            a = int(g.integers(0, s + 1))
+        na.append(a)
+        nb.append(s - a)
+    na, nb = np.array(na, np.int64), np.array(nb, np.int64)
+    A = np.concatenate([np.sort(g.integers(-(2**31), 2**31, k)).astype(np.int32) for k in na])
+    B = np.concatenate([np.sort(g.integers(-(2**31), 2**31, k)).astype(np.int32) for k in nb])
+    # a few pairs with heavy duplicates
+    A[: len(A) // 50] = np.sort(A[: len(A) // 50] % 5)
+    return A, gen.offsets(na), B, gen.offsets(nb)
+
+
+@pytest.mark.parametrize("shape", [(256, 8), (256, 16), (512, 16), (1024, 8), (1024, 16)])
+def test_batched_per_pair_tiles(mp, orc, shape):
+    """Batches through per-pair tiles (mode 1), every tile shape, against the
+    oracle, with guard canaries and two fills."""
+    from gpu_util import dev, first_mismatch
+    nt, vt = shape
+    A, a_off, B, b_off = _batch_edge_pairs(nt * vt, 120 + nt + vt)
+    # re-sort each A pair (the duplicate injection above may have broken order)
+    for k in range(len(a_off) - 1):
+        A[a_off[k]:a_off[k + 1]] = np.sort(A[a_off[k]:a_off[k + 1]])
+    want = orc.merge_batched(A, a_off, B, b_off)
+    dA, dB, da, db = dev(A), dev(B), dev(a_off), dev(b_off)
+    out = Guarded(len(A) + len(B), torch.int32, FILLS[0])
+    need = mp.merge_batched_workspace_bytes(torch.int32, len(a_off) - 1, len(A) + len(B))
+    ws = Guarded(need, torch.uint8, FILLS[1])
+    mp.set_config("batched", 1, nt, vt)
+    try:
+        for fill in FILLS:
+            out.refill(fill)
+            mp.merge_batched(dA, da, dB, db, out=out.view, ws=ws.view)
+            assert out.guards_intact() and ws.guards_intact()
+            assert first_mismatch(out.host(), want) is None, (shape, fill)
+    finally:
+        mp.set_config("batched", None)
+
+
+def test_batched_built_in_choice(mp, orc):
+    """The built-in batch configuration: per-pair tiles for a batch of long
+    pairs, the persistent kernel for a batch of short ones; both exact."""
+    from gpu_util import dev, first_mismatch
+    for median in (6000.0, 40.0):
+        A, a_off, B, b_off = gen.batched_pairs(2000, 121, median=median)
+        want = orc.merge_batched(A, a_off, B, b_off)
+        out = Guarded(len(A) + len(B), torch.int32, FILLS[0])
+        mp.merge_batched(dev(A), dev(a_off), dev(B), dev(b_off), out=out.view)
+        assert out.guards_intact()
+        assert first_mismatch(out.host(), want) is None, median
