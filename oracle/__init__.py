@@ -58,6 +58,8 @@ def _declare(lib):
         getattr(lib, f"oracle_sort_{n}").argtypes = [p, p, i64]
         getattr(lib, f"oracle_merge_batched_{n}").argtypes = [p, p, p, p, i64, p]
         getattr(lib, f"oracle_set_op_{n}").argtypes = [ctypes.c_int, p, i64, p, i64, p]
+        getattr(lib, f"oracle_join_{n}").argtypes = [p, i64, p, i64, p, p, i64]
+        getattr(lib, f"oracle_join_{n}").restype = i64
         getattr(lib, f"oracle_set_op_{n}").restype = i64
     return lib
 
@@ -149,3 +151,21 @@ def set_op(op: str, A, B, lib=None):
     S = np.empty(len(A) + len(B), dtype=A.dtype)
     k = getattr(lib, f"oracle_set_op_{n}")(SET_OPS[op], _ptr(A), len(A), _ptr(B), len(B), _ptr(S))
     return S[:k].copy()
+
+
+def join(A, B, cap: int | None = None, lib=None):
+    """Inner join of A and B: (I, J, count), the pairs with A[i] == B[j] in
+    (i, j) order (a nested loop: O(|A| |B|), for small inputs).  With cap,
+    only the first cap pairs are returned; count is always the total."""
+    lib = lib or load()
+    A = np.ascontiguousarray(A)
+    B = np.ascontiguousarray(B)
+    name = _key_name(A, B)
+    fn = getattr(lib, f"oracle_join_{name}")
+    if cap is None:
+        cap = fn(_ptr(A), len(A), _ptr(B), len(B), None, None, 0)
+    I = np.empty(max(cap, 1), dtype=np.int64)
+    J = np.empty(max(cap, 1), dtype=np.int64)
+    k = fn(_ptr(A), len(A), _ptr(B), len(B), _ptr(I), _ptr(J), cap)
+    m = min(k, cap)
+    return I[:m].copy(), J[:m].copy(), int(k)

@@ -18,7 +18,8 @@
  *   - batched:    independent merges of many (A_k, B_k) pairs written back to
  *                 back (Corollary 6 applied pair by pair);
  *   - set ops:    the multiset intersection, union, difference and symmetric
- *                 difference walked like the merge (matched equal heads).
+ *                 difference walked like the merge (matched equal heads);
+ *   - join:       every equal-key pair (i, j), by a nested loop.
  *
  * Key types: u32 and u64 compare unsigned, i32 signed, f32 with IEEE '<'/'>'
  * (so -0.0 and +0.0 tie, and the tie rule decides which bit pattern is output).
@@ -219,13 +220,41 @@ static int cmp_diag(const void *x, const void *y) {
     return k;                                                                  \
   }
 
+/*
+ * Inner join (the database join the introduction names as a use of the
+ * merge): every pair (i, j) with A[i] equal to B[j], by its definition, a
+ * nested loop over A then B, so the pairs come out ordered by i, then j.
+ * Equality is IEEE equality for floats (-0.0 equals +0.0).  The first `cap`
+ * pairs are written to I[] and J[]; returns the number of pairs.  (The
+ * equality test is overridable only so that a test can plant a mistake.)
+ */
+#ifndef ORACLE_JOIN_EQ
+#define ORACLE_JOIN_EQ(a, b) ((a) == (b))
+#endif
+#define DEFINE_JOIN(T, NAME)                                                   \
+  int64_t oracle_join_##NAME(const T *A, int64_t na, const T *B, int64_t nb,   \
+                             int64_t *I, int64_t *J, int64_t cap) {            \
+    int64_t k = 0;                                                             \
+    for (int64_t i = 0; i < na; ++i)                                           \
+      for (int64_t j = 0; j < nb; ++j)                                         \
+        if (ORACLE_JOIN_EQ(A[i], B[j])) {                                      \
+          if (k < cap) {                                                       \
+            I[k] = i;                                                          \
+            J[k] = j;                                                          \
+          }                                                                    \
+          ++k;                                                                 \
+        }                                                                      \
+    return k;                                                                  \
+  }
+
 #define DEFINE_ALL(T, NAME)                                                    \
   DEFINE_MERGE(T, NAME)                                                        \
   DEFINE_MERGE_KV(T, NAME)                                                     \
   DEFINE_PARTITION(T, NAME)                                                    \
   DEFINE_SORT(T, NAME)                                                         \
   DEFINE_BATCHED(T, NAME)                                                      \
-  DEFINE_SETOP(T, NAME)
+  DEFINE_SETOP(T, NAME)                                                        \
+  DEFINE_JOIN(T, NAME)
 
 DEFINE_ALL(uint32_t, u32)
 DEFINE_ALL(int32_t, i32)
