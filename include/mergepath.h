@@ -140,6 +140,30 @@ mp_status mp_set_op(int32_t op, mp_dtype kt, const void *A, int64_t na, const vo
                     void *stream);
 
 /*
+ * mp_join -- inner join of sorted A and B through the merge partition (the
+ * introduction names database joins among the merge's uses): every pair
+ * (i, j) with A[i] equal to B[j] (IEEE equality for f32, so -0.0 matches
+ * +0.0), ordered by i, then j.  A value found m times in A and n times in B
+ * gives its m x n pairs.  The merge's tiles (Algorithm 2 splits, Theorem 17
+ * inside a tile) give each A key the first B column of its run and the run's
+ * length; a scan gives each key its first output; the pairs are emitted by a
+ * second Merge Path merge, of those offsets with the output indices, in
+ * tiles of equal work whatever the duplicates.
+ *   I, J   room for `cap` int64 each (device): the first min(cap, count)
+ *          pairs, i in I and j in J; cap = 0 only counts.
+ *   count  one int64 (device, 8-byte aligned): the total number of pairs,
+ *          written when the work runs (may exceed cap: call again with room).
+ *   ws     device workspace of mp_join_workspace_bytes(na, nb) bytes
+ *          (about 16 bytes per A key), 8-byte aligned.
+ * I, J, count and ws must not overlap each other or the inputs.  Unsorted
+ * inputs give unspecified pairs and count but every store stays in bounds.
+ */
+size_t mp_join_workspace_bytes(int64_t na, int64_t nb);
+mp_status mp_join(mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb, int64_t *I,
+                  int64_t *J, int64_t cap, int64_t *count, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/*
  * mp_set_op_noalloc -- mp_set_op for callers that cannot allocate device
  * memory or pass a workspace (code under hipGraph capture, tight serving
  * loops, harnesses that forbid hipMalloc).  Same operation, arguments and

@@ -55,6 +55,8 @@ def _declare(L):
         "mp_set_op_workspace_bytes": ([i64, i64], ctypes.c_size_t),
         "mp_set_op": ([i32, i32, p, i64, p, i64, p, p, p, ctypes.c_size_t, p], i32),
         "mp_set_op_noalloc": ([i32, i32, p, i64, p, i64, p, p, p], i32),
+        "mp_join_workspace_bytes": ([i64, i64], ctypes.c_size_t),
+        "mp_join": ([i32, p, i64, p, i64, p, p, i64, p, p, ctypes.c_size_t, p], i32),
         "mp_merge_kv": ([i32, i32, p, p, i64, p, p, i64, p, p, p], i32),
         "mp_merge_batched_workspace_bytes": ([i32, i64, i64], sz),
         "mp_merge_batched": ([i32, p, p, p, p, i64, i64, i64, p, p, sz, p], i32),
@@ -261,6 +263,35 @@ def set_op(op: str, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None =
     if k < 0:
         raise RuntimeError("mp_set_op: a tile's wait for the tiles before it gave up")
     return out[:k]
+
+
+def join(A: torch.Tensor, B: torch.Tensor, cap: int | None = None, I=None, J=None, count=None,
+         ws=None, sync: bool = True):
+    """Inner join of sorted A and B: pairs (i, j) with A[i] == B[j] in
+    (i, j) order.  With sync (default) and cap None, counts first and
+    returns (I, J) trimmed to the count; otherwise returns (I, J, count)
+    with count an int64 device scalar (the total, which may exceed cap)."""
+    kt = _key_dtype(A, B)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=A.device)
+    need = lib().mp_join_workspace_bytes(A.numel(), B.numel())
+    if ws is None:
+        ws = torch.empty(max(need, 8), dtype=torch.uint8, device=A.device)
+    if cap is None and sync:
+        _check(lib().mp_join(kt, _ptr(A), A.numel(), _ptr(B), B.numel(), None, None, 0,
+                             _ptr(count), _ptr(ws), ws.numel(), _stream(A.device)))
+        cap = int(count.item())
+    cap = 0 if cap is None else cap
+    if I is None:
+        I = torch.empty(max(cap, 1), dtype=torch.int64, device=A.device)
+    if J is None:
+        J = torch.empty(max(cap, 1), dtype=torch.int64, device=A.device)
+    _check(lib().mp_join(kt, _ptr(A), A.numel(), _ptr(B), B.numel(), _ptr(I), _ptr(J), cap,
+                         _ptr(count), _ptr(ws), ws.numel(), _stream(A.device)))
+    if not sync:
+        return I, J, count
+    k = min(int(count.item()), cap)
+    return I[:k], J[:k]
 
 
 def set_op_noalloc(op: str, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor,

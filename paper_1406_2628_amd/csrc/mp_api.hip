@@ -296,6 +296,50 @@ mp_status mp_set_op_noalloc(int32_t op, mp_dtype kt, const void *A, int64_t na, 
                        stream);
 }
 
+size_t mp_join_workspace_bytes(int64_t na, int64_t nb) {
+  if (na < 0 || nb < 0 || na > INT64_MAX - nb) return 0;
+  return (size_t)join_ws_bytes(na, nb);
+}
+
+mp_status mp_join(mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb, int64_t *I,
+                  int64_t *J, int64_t cap, int64_t *count, void *ws, size_t ws_bytes,
+                  void *stream) {
+  const char *fn = "mp_join";
+  if (!is_key(kt)) return fail(MP_ERR_UNSUPPORTED, "%s: unsupported key dtype %d", fn, (int)kt);
+  const size_t es = dtype_size(kt);
+  mp_status st;
+  if ((st = check_array(A, na, es, "A")) != MP_OK) return st;
+  if ((st = check_array(B, nb, es, "B")) != MP_OK) return st;
+  if (na > INT64_MAX - nb) return fail(MP_ERR_INVALID_ARG, "%s: na + nb overflows", fn);
+  if (cap < 0) return fail(MP_ERR_INVALID_ARG, "%s: negative cap", fn);
+  if ((st = check_array(I, cap, 8, "I")) != MP_OK) return st;
+  if ((st = check_array(J, cap, 8, "J")) != MP_OK) return st;
+  if (!count || (uintptr_t)count % 8)
+    return fail(MP_ERR_INVALID_ARG, "%s: count must be an 8-byte aligned device pointer", fn);
+  const size_t need = mp_join_workspace_bytes(na, nb);
+  if (!ws || ws_bytes < need)
+    return fail(MP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+  if ((uintptr_t)ws % 8) return fail(MP_ERR_INVALID_ARG, "%s: workspace not 8-byte aligned", fn);
+  const Range ri = span(I, cap, 8), rj = span(J, cap, 8), rc = span(count, 1, 8);
+  const Range rw = span(ws, (int64_t)need, 1), ra = span(A, na, es), rb = span(B, nb, es);
+  const Range outs[] = {ri, rj, rc, rw};
+  for (int x = 0; x < 4; ++x) {
+    if (overlaps(outs[x], ra) || overlaps(outs[x], rb))
+      return fail(MP_ERR_OVERLAP, "%s: an output or the workspace overlaps an input", fn);
+    for (int y = x + 1; y < 4; ++y)
+      if (overlaps(outs[x], outs[y]))
+        return fail(MP_ERR_OVERLAP, "%s: I, J, count and the workspace must not overlap", fn);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  dispatch_key(kt, [&](auto k) {
+    using K = decltype(k);
+    KernelTimer timer("join", s);
+    e = launch_join<K>((const K *)A, na, (const K *)B, nb, I, J, cap, count, (int64_t *)ws, s);
+  });
+  return e == hipSuccess ? MP_OK : hip_fail(e, "mp_join launch");
+}
+
 mp_status mp_merge_split(mp_dtype kt, const void *A, int64_t na, const void *B, int64_t nb,
                          const int64_t *a_split, int32_t tile, void *S, void *stream) {
   const char *fn = "mp_merge_split";

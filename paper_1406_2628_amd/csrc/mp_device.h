@@ -137,4 +137,28 @@ __device__ __forceinline__ void serial_merge_inner(const K *keys, int ai, int bi
   }
 }
 
+// Inclusive scan of one value per lane across a workgroup of 1024 lanes
+// (every lane must call it); *total receives the sum over all lanes.
+// Calling it again needs a barrier first (its wave totals sit in LDS).
+__device__ __forceinline__ int64_t workgroup_scan1024(int64_t v, int64_t *total) {
+  __shared__ int64_t s_w[1024 / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(v, o);
+    if (lane >= o) v += y;
+  }
+  if (lane == 63) s_w[wave] = v;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < 1024 / 64; ++w) {
+    const int64_t t = s_w[w];
+    before += w < wave ? t : 0;
+    all += t;
+  }
+  *total = all;
+  return v + before;
+}
+
 }  // namespace mp

@@ -134,6 +134,14 @@ template <typename K>
 hipError_t launch_set_op(int op, const K *A, int64_t na, const K *B, int64_t nb, K *S,
                          int64_t cap, int64_t *count, int64_t *ws, hipStream_t s);
 
+// Inner join of sorted A and B: every (i, j) with A[i] == B[j], ordered by
+// i then j; the first cap pairs go to I and J, the total to *count (device).
+// ws: join_ws_bytes(na, nb) bytes, 8-byte aligned.
+int64_t join_ws_bytes(int64_t na, int64_t nb);
+template <typename K>
+hipError_t launch_join(const K *A, int64_t na, const K *B, int64_t nb, int64_t *I, int64_t *J,
+                       int64_t cap, int64_t *count, int64_t *ws, hipStream_t s);
+
 // Batched merge of CSR-concatenated pairs (persistent, one launch).
 template <typename K>
 hipError_t launch_merge_batched(StreamCfg cfg, const K *A, const int64_t *a_off,

@@ -1,0 +1,334 @@
+// Inner join of two sorted inputs through the merge partition: every pair
+// (i, j) with A[i] equal to B[j], ordered by i, then j.  The paper names
+// database joins among the uses of the merge (introduction); here the merge
+// path does the work twice.
+//
+// 1. Ranks (join_rank_kernel).  The merge's output tiles are cut by
+//    Algorithm 2 on their diagonals and each tile's pair is walked in LDS as
+//    in the merge (Theorem 17 for the lanes' splits, Lemma 1 for the walk).
+//    When the walk takes A[i] its column b is the first B position whose key
+//    is not below A[i] (ties take A first), so B's copies of A[i] are
+//    B[b, b + c); c is read off the B window (a search in LDS), and only a
+//    run that reaches the window's end continues in global memory.  Each A
+//    key gets lo[i] = b and c[i] = c.
+// 2. Offsets: an exclusive scan of c over A gives each A key the position of
+//    its first pair, and the total, which goes to *count.
+// 3. Pairs (join_emit_kernel), balanced whatever the duplicates: output p
+//    belongs to the last A key i with off[i] <= p.  That is again a merge:
+//    of off[] (non-decreasing) with the output indices 0, 1, 2, ..., ties
+//    taking off[] first, and output p then lies in the rows of key i at
+//    column p - off[i].  So the emission is the Merge Path merge of those two
+//    sequences: tiles of E items of the combined grid (keys and pairs
+//    together) split by Algorithm 2, each lane walking E / NT items.  The
+//    number of tiles is only known on the device (it depends on the count),
+//    so a grid of resident workgroups walks them.
+#include <stdint.h>
+
+#include "mp_device.h"
+#include "mp_internal.h"
+
+namespace mp {
+
+namespace {
+
+constexpr int kJoinNT = 256, kJoinVT = 16, kJoinT = kJoinNT * kJoinVT;  // rank tiles
+constexpr int kEmitNT = 256, kEmitVT = 8, kEmitE = kEmitNT * kEmitVT;     // emission tiles
+constexpr int kScanPer = 4;                                              // keys per scan lane
+constexpr int64_t kScanBlock = 1024 * kScanPer;
+
+template <typename K>
+__device__ __forceinline__ bool key_equal(K x, K y) {
+  return !(x < y) && !(y < x);
+}
+
+// First index in [lo, hi) of B whose key is above v (hi if none); B is
+// sorted.  Galloping from lo, then a binary search, so a short run costs
+// few probes.
+template <typename K>
+__device__ int64_t upper_from(const K *__restrict__ B, int64_t lo, int64_t hi, K v) {
+  int64_t step = 1, base = lo;
+  while (base + step <= hi && !(v < B[base + step - 1])) {
+    base += step;
+    step <<= 1;
+  }
+  int64_t l = base, h = base + step - 1 < hi ? base + step - 1 : hi;
+  while (l < h) {
+    const int64_t m = l + ((h - l) >> 1);
+    if (v < B[m]) h = m; else l = m + 1;
+  }
+  return l;
+}
+
+// Phase 1: per A key, its first column in B and the length of its B run.
+template <typename K>
+__global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
+    const K *__restrict__ A, int64_t na, const K *__restrict__ B, int64_t nb,
+    const int64_t *__restrict__ a_split, int64_t *__restrict__ lo_out,
+    int64_t *__restrict__ cnt_out) {
+  constexpr int NT = kJoinNT, VT = kJoinVT, T = kJoinT;
+  __shared__ K keys[T + VT + 1];
+  const int tid = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t N = na + nb;
+  const int64_t d0 = tile * T;
+  const int64_t d1 = d0 + T < N ? d0 + T : N;
+  const int n = (int)(d1 - d0);
+  // the tile's pair, clamped as in the merge so every access stays in bounds
+  const int64_t lo0 = d0 > nb ? d0 - nb : 0, hi0 = d0 < na ? d0 : na;
+  int64_t a0 = a_split[tile];
+  a0 = a0 < lo0 ? lo0 : (a0 > hi0 ? hi0 : a0);
+  const int64_t b0 = d0 - a0;
+  int64_t wa64 = a_split[tile + 1] - a0;
+  const int64_t wa_lo = d1 - nb - a0 > 0 ? d1 - nb - a0 : 0;
+  const int64_t wa_hi = na - a0 < (int64_t)n ? na - a0 : (int64_t)n;
+  wa64 = wa64 < wa_lo ? wa_lo : (wa64 > wa_hi ? wa_hi : wa64);
+  const int wa = (int)wa64, wb = n - wa;
+  const int64_t b1 = b0 + wb;  // first B key after the window
+  {
+    K r[VT];
+#pragma unroll
+    for (int s = 0; s < VT; ++s) {
+      const int i = tid + s * NT;
+      if (i < n) r[s] = i < wa ? A[a0 + i] : B[b0 + (i - wa)];
+    }
+#pragma unroll
+    for (int s = 0; s < VT; ++s) {
+      const int i = tid + s * NT;
+      if (i < n) keys[i] = r[s];
+    }
+  }
+  __syncthreads();
+  const int dl = tid * VT < n ? tid * VT : n;
+  int lo, hi;
+  diag_range<int>(dl, wa, wb, lo, hi);
+  const int a = split_search<int>(
+      dl, lo, hi, [&](int i) { return keys[i]; }, [&](int j) { return keys[wa + j]; });
+  int ai = a, bi = wa + (dl - a);
+  const int steps = n - dl < VT ? n - dl : VT;
+  bool have = false;  // this lane's last distinct A key and its run
+  K last{};
+  int64_t last_lo = 0, last_cnt = 0;
+  for (int s = 0; s < steps; ++s) {
+    const bool take_b = (bi < n) && (ai >= wa || keys[bi] < keys[ai]);
+    if (take_b) {
+      ++bi;
+      continue;
+    }
+    const K v = keys[ai];
+    const int64_t col = b0 + (bi - wa);  // first B position not below v
+    if (!have || !key_equal(v, last) || col != last_lo) {
+      int64_t c = 0;
+      if (bi < n) {
+        if (key_equal(keys[bi], v)) {
+          // B run of v inside the window: upper bound in LDS
+          int l = bi, h = n;
+          while (l < h) {
+            const int m = (l + h) >> 1;
+            if (v < keys[m]) h = m; else l = m + 1;
+          }
+          c = l - bi;
+          if (l == n) c += upper_from(B, b1, nb, v) - b1;  // run goes on past the window
+        }
+      } else if (b1 < nb && key_equal(B[b1], v)) {
+        c = upper_from(B, b1, nb, v) - b1;
+      }
+      have = true;
+      last = v;
+      last_lo = col;
+      last_cnt = c;
+    }
+    lo_out[a0 + ai] = last_lo;
+    cnt_out[a0 + ai] = last_cnt;
+    ++ai;
+  }
+}
+
+// Every A key starts with no run: keys that no tile visits (only possible
+// when unsorted inputs make the tiles' splits non-monotone) then count 0.
+__global__ void join_clear_kernel(int64_t *__restrict__ lo, int64_t *__restrict__ cnt, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    lo[i] = 0;
+    cnt[i] = 0;
+  }
+}
+
+// Phase 2a: sum of each block of kScanBlock counts.
+__global__ __launch_bounds__(1024) void join_scan_sums_kernel(const int64_t *__restrict__ cnt,
+                                                              int64_t n, int64_t *__restrict__ bsum) {
+  const int64_t k0 = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+  int64_t c = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i)
+    if (k0 + i < n) c += cnt[k0 + i];
+  int64_t total;
+  workgroup_scan1024(c, &total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Phase 2b (one workgroup): block sums to exclusive block offsets; the
+// grand total goes to *count.
+__global__ __launch_bounds__(1024) void join_scan_blocks_kernel(int64_t *__restrict__ bsum,
+                                                                int64_t n_blocks,
+                                                                int64_t *__restrict__ total_out,
+                                                                int64_t *__restrict__ count) {
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < n_blocks; b0 += 1024) {
+    const int64_t b = b0 + threadIdx.x;
+    const int64_t v = b < n_blocks ? bsum[b] : 0;
+    int64_t total;
+    const int64_t incl = workgroup_scan1024(v, &total);
+    __syncthreads();
+    if (b < n_blocks) bsum[b] = carry + incl - v;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    *total_out = carry;
+    *count = carry;
+  }
+}
+
+// Phase 2c: counts to exclusive offsets, in place.
+__global__ __launch_bounds__(1024) void join_scan_apply_kernel(int64_t *__restrict__ cnt, int64_t n,
+                                                               const int64_t *__restrict__ bsum) {
+  const int64_t k0 = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+  int64_t c[kScanPer], sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    c[i] = k0 + i < n ? cnt[k0 + i] : 0;
+    sum += c[i];
+  }
+  int64_t total;
+  int64_t t = workgroup_scan1024(sum, &total) - sum + bsum[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    if (k0 + i < n) cnt[k0 + i] = t;
+    t += c[i];
+  }
+}
+
+// Phase 3: the pairs.  off[0..na) offsets, off[na] the total (ws), lo[]
+// the first B column of every A key.  Resident workgroups walk the tiles of
+// the combined grid (na keys + total pairs) in strides.
+__global__ __launch_bounds__(kEmitNT) void join_emit_kernel(const int64_t *__restrict__ off,
+                                                            const int64_t *__restrict__ lo_col,
+                                                            int64_t na, int64_t *__restrict__ I,
+                                                            int64_t *__restrict__ J, int64_t cap) {
+  constexpr int NT = kEmitNT, VT = kEmitVT, E = kEmitE;
+  // off and lo of keys [a0 - 1, a1) (slot 0 is the key before the tile)
+  __shared__ int64_t s_off[E + 2], s_lo[E + 2];
+  __shared__ int64_t s_split[2];
+  const int tid = threadIdx.x;
+  const int64_t total = off[na];
+  const int64_t N = na + total;  // items of the combined grid
+  // A tile starting at item d0 emits outputs from d0 - na on, so tiles with
+  // d0 >= cap + na hold no output below cap: the walk stops before them
+  // (the work stays bounded by the caller's room, whatever the count).
+  const int64_t n_all = (N + E - 1) / E, n_room = (cap + na + E - 1) / E;
+  const int64_t n_tiles = n_all < n_room ? n_all : n_room;
+  // the split on diagonal d: off entries among the first d items (ties take
+  // off first: output p comes after every key with off <= p)
+  auto split_at = [&](int64_t d) -> int64_t {
+    int64_t l, h;
+    diag_range<int64_t>(d, na, total, l, h);
+    return group_split_search<64, int64_t>(
+        d, l, h, [&](int64_t i) { return off[i]; }, [&](int64_t j) { return j; });
+  };
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int64_t d0 = t * E;
+    const int64_t d1 = d0 + E < N ? d0 + E : N;
+    if (tid < 128) {
+      const int64_t a = split_at(tid < 64 ? d0 : d1);
+      if ((tid & 63) == 0) s_split[tid >> 6] = a;
+    }
+    __syncthreads();
+    const int64_t a0 = s_split[0], a1 = s_split[1];
+    const int64_t p0 = d0 - a0;  // first output of the tile
+    const int wa = (int)(a1 - a0);
+    const int n = (int)(d1 - d0);
+    for (int i = tid; i <= wa; i += NT) {
+      const int64_t k = a0 - 1 + i;
+      s_off[i] = k >= 0 ? off[k] : 0;
+      s_lo[i] = k >= 0 ? lo_col[k] : 0;
+    }
+    __syncthreads();
+    // lane split at local diagonal tid * VT: keys (s_off[1..]) against the
+    // outputs p0, p0 + 1, ...
+    const int dl = tid * VT < n ? tid * VT : n;
+    int lo, hi;
+    diag_range<int>(dl, wa, n - wa, lo, hi);
+    const int a = split_search<int>(
+        dl, lo, hi, [&](int i) { return s_off[1 + i]; }, [&](int j) { return p0 + j; });
+    int ai = a;                      // keys taken so far in the tile
+    int64_t p = p0 + (dl - a);       // next output
+    const int steps = n - dl < VT ? n - dl : VT;
+    for (int s = 0; s < steps; ++s) {
+      if (ai < wa && s_off[1 + ai] <= p) {
+        ++ai;  // key a0 + ai - 1 begins here
+      } else {
+        // output p: rows of key a0 + ai - 1
+        if (p < cap) {
+          I[p] = a0 + ai - 1;
+          J[p] = s_lo[ai] + (p - s_off[ai]);
+        }
+        ++p;
+      }
+    }
+    __syncthreads();  // the LDS windows are reused by the next tile
+  }
+}
+
+}  // namespace
+
+// Workspace: first B column per A key (na), counts then offsets (na + 1),
+// block sums of the scan, and the splits of the rank tiles.
+int64_t join_ws_bytes(int64_t na, int64_t nb) {
+  const int64_t n_blocks = (na + kScanBlock - 1) / kScanBlock;
+  const int64_t n_tiles = (na + nb + kJoinT - 1) / kJoinT;
+  return 8 * (na + (na + 1) + n_blocks + (n_tiles + 1));
+}
+
+template <typename K>
+hipError_t launch_join(const K *A, int64_t na, const K *B, int64_t nb, int64_t *I, int64_t *J,
+                       int64_t cap, int64_t *count, int64_t *ws, hipStream_t s) {
+  const int64_t n_blocks = (na + kScanBlock - 1) / kScanBlock;
+  const int64_t n_tiles = (na + nb + kJoinT - 1) / kJoinT;
+  int64_t *lo = ws, *off = lo + na, *bsum = off + (na + 1), *splits = bsum + n_blocks;
+  hipError_t e = hipSuccess;
+  if (na > 0)
+    hipLaunchKernelGGL(join_clear_kernel, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, lo,
+                       off, na);
+  if (n_tiles > 0) {
+    e = launch_partition<K>(A, na, B, nb, nullptr, kJoinT, n_tiles + 1, splits, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((join_rank_kernel<K>), dim3((unsigned)n_tiles), dim3(kJoinNT), 0, s, A, na,
+                       B, nb, splits, lo, off);
+  }
+  // (with no A keys the scan still writes the zero total)
+  if (n_blocks > 0)
+    hipLaunchKernelGGL(join_scan_sums_kernel, dim3((unsigned)n_blocks), dim3(1024), 0, s, off, na,
+                       bsum);
+  hipLaunchKernelGGL(join_scan_blocks_kernel, dim3(1), dim3(1024), 0, s, bsum, n_blocks, off + na,
+                     count);
+  if (n_blocks > 0)
+    hipLaunchKernelGGL(join_scan_apply_kernel, dim3((unsigned)n_blocks), dim3(1024), 0, s, off, na,
+                       bsum);
+  if (na > 0 && cap > 0) {
+    // resident workgroups walk the emission tiles
+    const int grid = 8 * device_cu_count();
+    hipLaunchKernelGGL(join_emit_kernel, dim3((unsigned)grid), dim3(kEmitNT), 0, s, off, lo, na, I,
+                       J, cap);
+  }
+  return hipGetLastError();
+}
+
+#define MP_INSTANTIATE(K)                                                                    \
+  template hipError_t launch_join<K>(const K *, int64_t, const K *, int64_t, int64_t *,      \
+                                     int64_t *, int64_t, int64_t *, int64_t *, hipStream_t);
+MP_INSTANTIATE(uint32_t)
+MP_INSTANTIATE(int32_t)
+MP_INSTANTIATE(uint64_t)
+MP_INSTANTIATE(float)
+#undef MP_INSTANTIATE
+
+}  // namespace mp

@@ -80,29 +80,6 @@ __device__ __forceinline__ int64_t batch_tiles(const TileArgs<K> &P, int64_t k, 
   return ((a1 - a0) + (b1 - b0) + T - 1) / T;
 }
 
-// Inclusive scan of one value per lane across the workgroup; *total gets
-// the sum of all lanes.
-__device__ __forceinline__ int64_t batch_block_scan(int64_t v, int64_t *total) {
-  __shared__ int64_t s_w[kBatchLanes / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int64_t y = __shfl_up(v, o);
-    if (lane >= o) v += y;
-  }
-  if (lane == 63) s_w[wave] = v;
-  __syncthreads();
-  int64_t before = 0, all = 0;
-#pragma unroll
-  for (int w = 0; w < kBatchLanes / 64; ++w) {
-    const int64_t t = s_w[w];
-    before += w < wave ? t : 0;
-    all += t;
-  }
-  *total = all;
-  return v + before;
-}
-
 // Pass 1: tiles of each block of pairs.
 template <typename K>
 __global__ __launch_bounds__(kBatchLanes) void batch_count_kernel(TileArgs<K> P, int64_t T) {
@@ -112,7 +89,7 @@ __global__ __launch_bounds__(kBatchLanes) void batch_count_kernel(TileArgs<K> P,
   for (int i = 0; i < kBatchPer; ++i)
     if (k0 + i < P.n_pairs) c += batch_tiles(P, k0 + i, T);
   int64_t total;
-  batch_block_scan(c, &total);
+  workgroup_scan1024(c, &total);
   if (threadIdx.x == 0) P.bsum[blockIdx.x] = total;
 }
 
@@ -124,7 +101,7 @@ __global__ __launch_bounds__(kBatchLanes) void batch_sums_kernel(TileArgs<K> P, 
     const int64_t b = b0 + threadIdx.x;
     const int64_t v = b < n_blocks ? P.bsum[b] : 0;
     int64_t total;
-    const int64_t incl = batch_block_scan(v, &total);
+    const int64_t incl = workgroup_scan1024(v, &total);
     __syncthreads();  // every lane has read s_w before the next round writes it
     if (b < n_blocks) P.bsum[b] = carry + incl - v;
     carry += total;
@@ -143,7 +120,7 @@ __global__ __launch_bounds__(kBatchLanes) void batch_fill_kernel(TileArgs<K> P, 
     sum += c[i];
   }
   int64_t total;
-  int64_t t = batch_block_scan(sum, &total) - sum + P.bsum[blockIdx.x];
+  int64_t t = workgroup_scan1024(sum, &total) - sum + P.bsum[blockIdx.x];
 #pragma unroll
   for (int i = 0; i < kBatchPer; ++i) {
     const int64_t k = k0 + i;

@@ -93,6 +93,21 @@ def test_set_op_noalloc_argument_errors(L):
     assert b"scratch" in L.mp_last_error()
 
 
+def test_join_argument_errors(L):
+    a, b, i, j, c, w = P(0x10000), P(0x20000), P(0x30000), P(0x40000), P(0x50000), P(0x60000)
+    need = L.mp_join_workspace_bytes(10, 10)
+    assert need > 0
+    assert L.mp_join(0, a, 10, b, 10, i, j, 5, c, w, need, None) == UNSUPPORTED
+    assert L.mp_join(MP_U32, a, 10, b, 10, i, j, -1, c, w, need, None) == INVALID
+    assert L.mp_join(MP_U32, a, 10, b, 10, i, j, 5, None, w, need, None) == INVALID
+    assert L.mp_join(MP_U32, a, 10, b, 10, None, j, 5, c, w, need, None) == INVALID
+    assert L.mp_join(MP_U32, a, 10, b, 10, i, j, 5, c, None, 0, None) == WORKSPACE
+    assert L.mp_join(MP_U32, a, 10, b, 10, i, j, 5, c, w, need - 8, None) == WORKSPACE
+    assert L.mp_join(MP_U32, a, 10, b, 10, i, j, 5, c, P(0x60004), need, None) == INVALID
+    assert L.mp_join(MP_U32, a, 10, b, 10, P(0x10000 + 8), j, 5, c, w, need, None) == OVERLAP
+    assert L.mp_join(MP_U32, a, 10, b, 10, i, P(0x30000 + 16), 5, c, w, need, None) == OVERLAP
+
+
 def test_merge_split_argument_errors(L):
     a, b, sp, s = P(0x10000), P(0x20000), P(0x30000), P(0x40000)
     assert L.mp_merge_split(MP_U32, a, 10, b, 10, sp, 1000, s, None) == UNSUPPORTED
