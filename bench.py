@@ -11,8 +11,8 @@ kernel timed with HIP events that the library records on its launch stream,
 the single-core oracle baseline timed on the host, the same merge kept in
 registers (nothing stored), and under "extras" the other workloads: a small
 cache-resident merge (hot and cold), key-value merges, merge sort, batched
-merge, the learned split predictor against the plain split search, and the
-multiset operations.  Every output is checked
+merge, the learned split predictor against the plain split search, the
+multiset operations and the inner join.  Every output is checked
 (bit-exact against the oracle, or for the 2^28 sort against numpy's sort,
 which the oracle's own tests pin).
 
@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gkeys/s merged & % HBM peak (2^28+2^28 u32); learned vs bsearch split time"
-LEGS = ("headline", "small", "kv", "sort", "batched", "learned", "setops")
+LEGS = ("headline", "small", "kv", "sort", "batched", "learned", "setops", "join")
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "merge_tile_u32_2p28.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1406_2628_amd", "csrc", f)
                   for f in ("mp_tile_impl.h", "mp_device.h")]
@@ -352,6 +352,44 @@ def leg_setops(args, ex):
 
 
 # ---------------------------------------------------------------------------
+def leg_join(args, ex):
+    """Inner join of 2^26 + 2^26 sorted u32 keys drawn from [0, 2^27) (seed
+    93): every equal-key pair (i, j).  The count is checked against the
+    closed form sum over values of (copies in A) x (copies in B), and 2^20
+    sampled pairs for equal keys and (i, j) order."""
+    import numpy as np
+    import torch
+
+    import paper_1406_2628_amd as mp
+    n = 1 << (args.log2n - 2)
+    log(f"bench: join 2^{n.bit_length() - 1}+2^{n.bit_length() - 1} u32")
+    g = np.random.default_rng(93)
+    A = np.sort(g.integers(0, 2 * n, n, dtype=np.uint32))
+    B = np.sort(g.integers(0, 2 * n, n, dtype=np.uint32))
+    dA, dB = dev(A), dev(B)
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    ws = torch.empty(mp.lib().mp_join_workspace_bytes(n, n), dtype=torch.uint8, device="cuda")
+    mp.join(dA, dB, cap=0, count=cnt, ws=ws, sync=False)
+    k = int(cnt.item())
+    I = torch.empty(max(k, 1), dtype=torch.int64, device="cuda")
+    J = torch.empty_like(I)
+    ms = time_steps(lambda: mp.join(dA, dB, cap=k, I=I, J=J, count=cnt, ws=ws, sync=False),
+                    max(3, args.steps // 2), 2)
+    lo, hi = np.searchsorted(B, A, "left"), np.searchsorted(B, A, "right")
+    want = int(np.sum(hi - lo))
+    idx = np.sort(np.random.default_rng(0).integers(0, max(k, 1), 1 << 20))
+    hi_, hj = I.cpu().numpy()[idx], J.cpu().numpy()[idx]
+    ordered = bool(np.all((np.diff(hi_) > 0) | ((np.diff(hi_) == 0) & (np.diff(hj) >= 0))))
+    # fewest bytes: both inputs once, each pair (two int64) once
+    bytes_ = 2 * n * 4 + k * 16
+    ex["join"] = {"n_per_input": n, "pairs": k, "ms": round(ms, 4),
+                  "Gpairs_s": round(k / ms / 1e6, 2),
+                  "hbm_frac_min_bytes": round(bytes_ / ms / 1e6 / HBM_PEAK_GBS, 4),
+                  "count_matches_closed_form": k == want,
+                  "sampled_pairs_equal_and_ordered": bool(np.all(A[hi_] == B[hj])) and ordered}
+
+
+# ---------------------------------------------------------------------------
 def leg_kv(args, ex):
     import torch
 
@@ -550,7 +588,7 @@ def leg_learned(args, ex):
     res["oracle_spot_check_256"] = bool(np.array_equal(got, oracle.partition(Ah, Bh, ds)))
     # the full f32 merge (Algorithm 1 in two calls) on learned splits of the
     # 2048-key tile diagonals, against the same on plain splits and against
-    # the persistent merge
+    # the built-in merge (its own tile splits, then its tiles)
     log("bench: learned: full f32 merge on learned splits")
     T = 2048
     tdiag = torch.clamp(torch.arange((N + T - 1) // T + 1, device="cuda", dtype=torch.int64) * T,
@@ -568,7 +606,7 @@ def leg_learned(args, ex):
         "n": N, "tile": T, "tiles": int(tdiag.numel() - 1),
         "learned_split_ms": round(t_pl, 4), "plain_split_ms": round(t_pp, 4),
         "tile_merge_ms": round(t_mt, 4), "total_learned_ms": round(t_pl + t_mt, 4),
-        "total_plain_ms": round(t_pp + t_mt, 4), "persistent_merge_ms": round(t_ps, 4),
+        "total_plain_ms": round(t_pp + t_mt, 4), "builtin_merge_ms": round(t_ps, 4),
         "splits_identical": bool(torch.equal(sp_l, sp_p)),
         "bit_exact": bool(got.tobytes() == ref.tobytes())}
     ex["learned"] = res
@@ -577,8 +615,8 @@ def leg_learned(args, ex):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--log2n", type=int, default=28, help="log2 of |A| = |B| for the headline")
     ap.add_argument("--legs", default=",".join(LEGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -606,7 +644,8 @@ def main():
         leg_headline(args, out)
     ex = {}
     for name, fn in (("small", leg_small), ("kv", leg_kv), ("sort", leg_sort),
-                     ("batched", leg_batched), ("learned", leg_learned), ("setops", leg_setops)):
+                     ("batched", leg_batched), ("learned", leg_learned), ("setops", leg_setops),
+                     ("join", leg_join)):
         if name in legs:
             fn(args, ex)
             torch.cuda.empty_cache()

@@ -45,7 +45,9 @@
 // remains for a workgroup's first tile and as an option.
 #pragma once
 
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "mp_device.h"
 #include "mp_internal.h"
@@ -818,17 +820,28 @@ static hipError_t launch_pairs_impl(int grid, bool vec, PairArgs<K> args, hipStr
   args.stats = stats_device_ptr();
   if (args.n_tiles == 0) return hipSuccess;
   if (grid <= 0) {
-    // one full wave of resident workgroups
-    static int per_cu = 0;
-    if (per_cu == 0) {
-      int occ = 0;
+    // one full wave of resident workgroups (occupancy queried once per
+    // device and kernel; the answer is the same for every device of one
+    // kind, but a process may mix kinds)
+    static std::mutex mu;
+    static std::vector<int> per_cu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    int occ = 0;
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      if ((int)per_cu.size() <= dev) per_cu.resize(dev + 1, 0);
+      occ = per_cu[dev];
+    }
+    if (occ == 0) {
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
               &occ, merge_pairs_kernel<K, KV, NT, VT, KIND, true, STORE>, NT, 0) != hipSuccess ||
           occ <= 0)
         occ = 1;
-      per_cu = occ;
+      std::lock_guard<std::mutex> lock(mu);
+      per_cu[dev] = occ;
     }
-    grid = per_cu * device_cu_count();
+    grid = occ * device_cu_count();
   }
   g_last_pairs_grid = grid;
   const int64_t G = grid < args.n_tiles ? grid : args.n_tiles;
