@@ -189,7 +189,8 @@ mp_status mp_set_op_noalloc(int32_t op, mp_dtype kt, const void *A, int64_t na, 
  *   a_split  ceil((na+nb)/tile) + 1 int64 splits (device) on the diagonals
  *            min(k*tile, na+nb): what mp_partition or mp_partition_learned
  *            return for those diagonals.
- *   tile     2048, 3840 or 4096 outputs per tile (MP_ERR_UNSUPPORTED else).
+ *   tile     2048, 3840, 4096, 8192 or 16384 outputs per tile
+ *            (MP_ERR_UNSUPPORTED else).
  *   S        na+nb keys, must overlap neither input nor a_split.
  * The result is the merge when the splits are the true ones.  Other split
  * values give some other output but stay memory-safe: every split is

@@ -105,7 +105,7 @@ def _tile_diagonals(n, tile):
     return np.minimum(np.arange((n + tile - 1) // tile + 1, dtype=np.int64) * tile, n)
 
 
-@pytest.mark.parametrize("tile", [2048, 3840, 4096])
+@pytest.mark.parametrize("tile", [2048, 3840, 4096, 8192, 16384])
 def test_merge_split_from_partition(mp, orc, tile):
     """Algorithm 1 in two calls: splits on the tile diagonals, then the tiles
     merged independently, gives the oracle's merge."""
