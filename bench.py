@@ -488,7 +488,7 @@ def leg_batched(args, ex):
     tuned = autotune.tune_batched(dA, da, dB, db, dS, reps=3)
     mp.graph_mode(True)
     mp.timing_enable(True)
-    ms = time_steps(lambda: mp.merge_batched(dA, da, dB, db, out=dS), args.steps, 2)
+    ms = time_steps(lambda: mp.merge_batched(dA, da, dB, db, out=dS), args.steps, 10)
     tiles, reloads = mp.stats_query()
     mp.timing_enable(False)
     mp.graph_mode(False)

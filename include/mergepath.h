@@ -189,8 +189,8 @@ mp_status mp_set_op_noalloc(int32_t op, mp_dtype kt, const void *A, int64_t na, 
  *   a_split  ceil((na+nb)/tile) + 1 int64 splits (device) on the diagonals
  *            min(k*tile, na+nb): what mp_partition or mp_partition_learned
  *            return for those diagonals.
- *   tile     2048, 3840, 4096, 8192 or 16384 outputs per tile
- *            (MP_ERR_UNSUPPORTED else).
+ *   tile     2048, 3840, 4096, 8192 or 16384 outputs per tile; 16384 for
+ *            4-byte keys only (MP_ERR_UNSUPPORTED else).
  *   S        na+nb keys, must overlap neither input nor a_split.
  * The result is the merge when the splits are the true ones.  Other split
  * values give some other output but stay memory-safe: every split is
@@ -232,7 +232,9 @@ mp_status mp_merge_kv(mp_dtype kt, mp_dtype vt, const void *Ak, const void *Av,
 /*
  * mp_merge_batched -- many independent merges in one launch (Corollary 6
  * applied to a concatenation of pairs; Corollary 7 load balance over the
- * global output index).
+ * global output index).  The batch is merged as one merge of the
+ * concatenated inputs in (pair, key) order, cut into equal tiles of the
+ * global output that may span many pairs.
  *   A, a_off  concatenated A_k; a_off has n_pairs+1 int64 entries (device),
  *             a_off[0] = 0, non-decreasing; A_k = A[a_off[k], a_off[k+1])
  *   B, b_off  likewise for B_k
@@ -242,6 +244,8 @@ mp_status mp_merge_kv(mp_dtype kt, mp_dtype vt, const void *Ak, const void *Av,
  *             used to size the launch; must match the device offsets)
  *   ws, ws_bytes  device workspace of at least
  *             mp_merge_batched_workspace_bytes(kt, n_pairs, total_a+total_b)
+ *             bytes (12 bytes per 2048 outputs), 8-byte aligned, overlapping
+ *             nothing else; the persistent configuration (mode 2) needs none.
  * Offsets are not validated on the device; non-monotone offsets give an
  * unspecified result with in-bounds accesses.
  */

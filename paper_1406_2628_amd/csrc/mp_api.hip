@@ -60,10 +60,8 @@ const mp_config kDefaultConfig[kNumOps] = {
     {1, 0, 0, 0, 0},     // batched
     {1, 0, 0, 0, 0},     // sort rounds
 };
-// Batches whose mean pair is shorter than this many keys stay on the
-// persistent kernel in the built-in configuration: per-pair tiles would
-// leave most lanes of each tile idle.
-constexpr int64_t kBatchTileMinMeanPair = 1024;
+// Batches too large for 32-bit pair and tile indices stay on the persistent
+// kernel in the built-in configuration.
 const mp_config kBatchedPersistent = {2, 256, 16, 0, 0};
 // The persistent shape the no-store diagnostic uses when the merge is not
 // set to a persistent shape that has a no-store variant.
@@ -97,16 +95,17 @@ mp_status set_error(mp_status st, const char *fmt, ...) {
 
 // Largest tile of the key's ladder that still leaves at least two tiles per
 // compute unit (smaller tiles only for small merges).  The ladders keep a
-// tile's LDS at or under 64 KB: 16384 keys of 4 bytes (1024 x 16), 8192 of
+// tile's LDS at or under 72 KB: 16384 keys of 4 bytes (1024 x 16), 8192 of
 // 8 bytes (1024 x 8) or of 4 bytes with values (512 x 16: 3-5% faster than
-// 1024 x 8), 4096 of 8 bytes with values.
+// 1024 x 8), 6144 of 8 bytes with values (512 x 12: 1.11 against 1.17 ms
+// for 2^27 + 2^27 u64 keys with values at 256 x 16).
 TileCfg auto_tile_cfg(size_t key_bytes, bool kv, int64_t n) {
   static const TileCfg k4[] = {{1024, 16}, {512, 16}, {256, 16}, {256, 8}};
   static const TileCfg k4v[] = {{512, 16}, {256, 16}, {256, 8}};
   static const TileCfg k8[] = {{1024, 8}, {256, 16}, {256, 8}};
-  static const TileCfg k8v[] = {{256, 16}, {256, 8}};
+  static const TileCfg k8v[] = {{512, 12}, {256, 16}, {256, 8}};
   const TileCfg *lad = key_bytes == 8 ? (kv ? k8v : k8) : (kv ? k4v : k4);
-  const int len = key_bytes == 8 ? (kv ? 2 : 3) : (kv ? 3 : 4);
+  const int len = key_bytes == 8 ? 3 : (kv ? 3 : 4);
   const int64_t want = 2 * (int64_t)device_cu_count();
   for (int i = 0; i < len; ++i)
     if (n / ((int64_t)lad[i].nt * lad[i].vt) >= want) return lad[i];
@@ -488,7 +487,7 @@ mp_status mp_bw_probe(int32_t kind, const void *src, void *dst, int64_t n_bytes,
 size_t mp_merge_batched_workspace_bytes(mp_dtype kt, int64_t n_pairs, int64_t total) {
   (void)kt;
   if (n_pairs < 0 || total < 0) return 0;
-  return (size_t)batch_tile_ws_bytes(n_pairs, total);
+  return (size_t)batch_tile_ws_bytes(total);
 }
 
 mp_status mp_merge_batched(mp_dtype kt, const void *A, const int64_t *a_off,
@@ -516,16 +515,16 @@ mp_status mp_merge_batched(mp_dtype kt, const void *A, const int64_t *a_off,
   if (n == 0) return MP_OK;
   mp_config cfg = current_config(kOpBatched);
   TileCfg tc{cfg.nt, cfg.vt};
-  // per-pair tiles index pairs with 32-bit integers and launch one
-  // workgroup per possible tile
-  const bool tiles_fit = n_pairs < ((int64_t)1 << 30) && n / kBatchMinTile + n_pairs < INT32_MAX;
+  // batch tiles index pairs and tiles with 32-bit integers
+  const bool tiles_fit = n_pairs < INT32_MAX && (n + kBatchMinTile - 1) / kBatchMinTile < INT32_MAX;
   if (cfg.mode == 1 && cfg.nt == 0) {
-    // built-in: 4096-key tiles per pair, or the persistent kernel for short pairs
-    if (n < kBatchTileMinMeanPair * n_pairs || !tiles_fit) cfg = kBatchedPersistent;
+    // built-in: 4096-key tiles (256 x 16 measured best from pairs of 64 to
+    // 5000 keys), or the persistent kernel past the 32-bit indices
+    if (!tiles_fit) cfg = kBatchedPersistent;
     else tc = TileCfg{256, 16};
   }
   if (cfg.mode == 1 && !tiles_fit)
-    return fail(MP_ERR_UNSUPPORTED, "%s: per-pair tiles take fewer than 2^30 pairs", fn);
+    return fail(MP_ERR_UNSUPPORTED, "%s: batch tiles take fewer than 2^31 - 1 pairs", fn);
   if (cfg.mode == 1) {
     const size_t need = mp_merge_batched_workspace_bytes(kt, n_pairs, n);
     if (!ws || ws_bytes < need)

@@ -73,20 +73,15 @@ template <typename K>
 hipError_t launch_sort_round_tiles(TileCfg cfg, const K *X, const uint32_t *Xv, K *Y,
                                    uint32_t *Yv, int64_t n, int lw, hipStream_t s);
 
-// Batch of independent pairs through the per-tile merge: every pair cut into
-// its own tiles (keys only; tiles of at least kBatchMinTile outputs).  ws:
-// batch_tile_ws_bytes(n_pairs, total) bytes, 8-byte aligned.
+// Batch of independent pairs through the per-tile merge, merged as one merge
+// of the concatenated inputs in (pair, key) order (keys only; tiles of at
+// least kBatchMinTile outputs).  ws: batch_tile_ws_bytes(total) bytes,
+// 8-byte aligned: the splits of the tile boundaries (int64 each) and the pair
+// holding each tile's first output (int32 each).
 constexpr int64_t kBatchMinTile = 2048;
-// The batch's pairs are counted and scanned in blocks of 1024 lanes x 4 pairs.
-constexpr int kBatchLanes = 1024, kBatchPer = 4;
-constexpr int64_t kBatchPairsPerBlock = (int64_t)kBatchLanes * kBatchPer;
-// Workspace: the first tile of every pair (n_pairs + 1 int64), the tile
-// counts of the blocks of pairs (int64 each) and the pair of every possible
-// tile (int32; at most total / kBatchMinTile + n_pairs tiles).
-inline int64_t batch_tile_ws_bytes(int64_t n_pairs, int64_t total) {
-  const int64_t n_blocks = (n_pairs + kBatchPairsPerBlock - 1) / kBatchPairsPerBlock;
-  const int64_t max_tiles = (total + kBatchMinTile - 1) / kBatchMinTile + n_pairs;
-  return 8 * (n_pairs + 1) + 8 * n_blocks + 4 * max_tiles;
+inline int64_t batch_tile_ws_bytes(int64_t total) {
+  const int64_t tiles = (total + kBatchMinTile - 1) / kBatchMinTile;
+  return 8 * (tiles + 1) + 4 * tiles;
 }
 template <typename K>
 hipError_t launch_merge_batched_tiles(TileCfg cfg, const K *A, const int64_t *a_off, const K *B,

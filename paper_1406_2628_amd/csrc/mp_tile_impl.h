@@ -22,15 +22,14 @@
 // Layouts: kSingle merges (A, B); kRuns is one round of merge sort over X:
 // pair k is (X[2wk, 2wk+w), X[2wk+w, 2wk+2w)) clipped to n, left run as A
 // (stable), and tiles (a power of two dividing 2w) never cross a pair end,
-// so every tile is again one plain pair of ranges of X.  kExplicit is a
-// batch of independent pairs given by CSR offsets (Corollary 6 pair by
-// pair): each pair is cut into its own tiles of at most T outputs, tile j of
-// pair k writing S[out(k) + jT, ...) with out(k) = a_off(k) + b_off(k), so
-// again no tile crosses a pair end.  Their number is only known on the
-// device: a count-and-scan over the pairs builds the first tile of every
-// pair and the pair of every tile in the caller's workspace, and the
-// launches cover an upper bound (N / T + pairs), surplus workgroups exiting
-// at once.
+// so every tile is again one plain pair of ranges of X.  kBatch is a batch
+// of independent pairs given by CSR offsets (Corollary 6 pair by pair),
+// merged as one merge of the concatenated inputs in (pair, key) order: its
+// tiles of T outputs cross pair ends, each is one contiguous window of A and
+// of B, and a lane whose outputs cross a pair end switches pairs there.  Its
+// splits and the pair of each tile's first output go to the caller's
+// workspace (a batch has one, and a tile can be shorter than a header only
+// at the very end).
 #pragma once
 
 #include "mp_device.h"
@@ -38,7 +37,7 @@
 
 namespace mp {
 
-enum TileKind { kTileSingle = 0, kTileRuns = 1, kTileExplicit = 2 };
+enum TileKind { kTileSingle = 0, kTileRuns = 1, kTileBatch = 2 };
 enum TileSrc { kTileHeader = 0, kTileSplitArray = 1 };
 
 template <typename K>
@@ -50,14 +49,13 @@ struct TileArgs {
   int64_t NA, NB;           // lengths of A and B (kTileRuns: n and n)
   int64_t N;                // outputs (kTileSingle: NA + NB; kTileRuns: n)
   int lw;                   // kTileRuns: log2 of the run width
-  const int64_t *a_split;   // kTileSplitArray: the caller's splits
-  int64_t n_tiles;          // kTileExplicit: an upper bound of the tile count
-  // kTileExplicit
+  const int64_t *a_split;   // kTileSplitArray: the splits of the tiles
+  int64_t n_tiles;
+  // kTileBatch
   const int64_t *a_off, *b_off;  // CSR offsets of the pairs (n_pairs + 1)
   int64_t n_pairs;
-  int64_t *tile_off;        // first tile of each pair (n_pairs + 1; workspace)
-  int32_t *tile_pair;       // pair of each tile (workspace)
-  int64_t *bsum;            // tile counts of blocks of pairs (workspace)
+  int64_t *split_out;       // the splits step 1 writes (n_tiles + 1; workspace)
+  int32_t *tile_pair;       // pair holding each tile's first output (workspace)
 };
 
 // Pair k of a batch with its offsets kept inside the arrays and
@@ -72,67 +70,58 @@ __device__ __forceinline__ void batch_pair(const TileArgs<K> &P, int64_t k, int6
   b1 = clamp(P.b_off[k + 1], b0, P.NB);
 }
 
-// ---- tiles of a batch: count, scan, fill ------------------------------------
+// ---- a batch as one merge of its concatenations ---------------------------
+// With pair k owning A[a_off(k), a_off(k+1)), B[b_off(k), b_off(k+1)) and
+// the outputs [o(k), o(k+1)), o(k) = a_off(k) + b_off(k), the batch is one
+// merge of the concatenated A and B in the order (pair, key): the split on a
+// global diagonal D inside pair p is (a_off(p) + a, b_off(p) + D - o(p) - a)
+// with a the split of pair p on its own diagonal D - o(p), and A + B counts
+// add up to D again.  So the batch is cut into tiles of T outputs like a
+// single merge, each tile one contiguous window of A and of B, and only a
+// lane whose outputs cross a pair end needs to know more.
+
+// Offsets of pair k's start, kept inside the arrays (no-ops when valid).
 template <typename K>
-__device__ __forceinline__ int64_t batch_tiles(const TileArgs<K> &P, int64_t k, int64_t T) {
+__device__ __forceinline__ int64_t batch_a_at(const TileArgs<K> &P, int64_t k) {
+  const int64_t v = P.a_off[k];
+  return v < 0 ? 0 : (v > P.NA ? P.NA : v);
+}
+template <typename K>
+__device__ __forceinline__ int64_t batch_b_at(const TileArgs<K> &P, int64_t k) {
+  const int64_t v = P.b_off[k];
+  return v < 0 ? 0 : (v > P.NB ? P.NB : v);
+}
+
+// The pair holding global output D, searched from pair p (o(p) <= D): the
+// last k in [p, n_pairs) with o(k) <= D, galloping from p then bisecting
+// (one probe when D lies in pair p).
+template <typename K>
+__device__ __forceinline__ int64_t batch_pair_of(const TileArgs<K> &P, int64_t p, int64_t D) {
+  int64_t step = 1;
+  while (p + step < P.n_pairs && batch_a_at(P, p + step) + batch_b_at(P, p + step) <= D) {
+    p += step;
+    step <<= 1;
+  }
+  int64_t lo = p + 1, hi = p + step < P.n_pairs ? p + step : P.n_pairs;
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (batch_a_at(P, mid) + batch_b_at(P, mid) <= D) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo - 1;
+}
+
+// Pair holding the first output of every tile: each nonempty pair k writes
+// itself for the tiles that start inside [o(k), o(k+1)).
+template <typename K>
+__global__ __launch_bounds__(256) void batch_bound_kernel(TileArgs<K> P, int64_t T) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= P.n_pairs) return;
   int64_t a0, a1, b0, b1;
   batch_pair(P, k, a0, a1, b0, b1);
-  return ((a1 - a0) + (b1 - b0) + T - 1) / T;
-}
-
-// Pass 1: tiles of each block of pairs.
-template <typename K>
-__global__ __launch_bounds__(kBatchLanes) void batch_count_kernel(TileArgs<K> P, int64_t T) {
-  const int64_t k0 = (int64_t)blockIdx.x * kBatchPairsPerBlock + (int64_t)threadIdx.x * kBatchPer;
-  int64_t c = 0;
-#pragma unroll
-  for (int i = 0; i < kBatchPer; ++i)
-    if (k0 + i < P.n_pairs) c += batch_tiles(P, k0 + i, T);
-  int64_t total;
-  workgroup_scan1024(c, &total);
-  if (threadIdx.x == 0) P.bsum[blockIdx.x] = total;
-}
-
-// Pass 2 (one workgroup): block counts to exclusive block offsets, in place.
-template <typename K>
-__global__ __launch_bounds__(kBatchLanes) void batch_sums_kernel(TileArgs<K> P, int64_t n_blocks) {
-  int64_t carry = 0;
-  for (int64_t b0 = 0; b0 < n_blocks; b0 += kBatchLanes) {
-    const int64_t b = b0 + threadIdx.x;
-    const int64_t v = b < n_blocks ? P.bsum[b] : 0;
-    int64_t total;
-    const int64_t incl = workgroup_scan1024(v, &total);
-    __syncthreads();  // every lane has read s_w before the next round writes it
-    if (b < n_blocks) P.bsum[b] = carry + incl - v;
-    carry += total;
-  }
-}
-
-// Pass 3: first tile of every pair (and the tile total), and the pair of
-// every tile.
-template <typename K>
-__global__ __launch_bounds__(kBatchLanes) void batch_fill_kernel(TileArgs<K> P, int64_t T) {
-  const int64_t k0 = (int64_t)blockIdx.x * kBatchPairsPerBlock + (int64_t)threadIdx.x * kBatchPer;
-  int64_t c[kBatchPer], sum = 0;
-#pragma unroll
-  for (int i = 0; i < kBatchPer; ++i) {
-    c[i] = k0 + i < P.n_pairs ? batch_tiles(P, k0 + i, T) : 0;
-    sum += c[i];
-  }
-  int64_t total;
-  int64_t t = workgroup_scan1024(sum, &total) - sum + P.bsum[blockIdx.x];
-#pragma unroll
-  for (int i = 0; i < kBatchPer; ++i) {
-    const int64_t k = k0 + i;
-    if (k < P.n_pairs) {
-      P.tile_off[k] = t;
-      // (offsets that overlap across pairs could count more tiles than the
-      // launches cover; those are never launched and get no entry)
-      for (int64_t j = 0; j < c[i] && t + j < P.n_tiles; ++j) P.tile_pair[t + j] = (int32_t)k;
-      t += c[i];
-      if (k == P.n_pairs - 1) P.tile_off[P.n_pairs] = t;
-    }
-  }
+  const int64_t o0 = a0 + b0, o1 = a1 + b1;
+  const int64_t t_end = (o1 + T - 1) / T < P.n_tiles ? (o1 + T - 1) / T : P.n_tiles;
+  for (int64_t t = (o0 + T - 1) / T; t < t_end; ++t) P.tile_pair[t] = (int32_t)k;
 }
 
 // Header bytes at the start of each tile's range of S.
@@ -178,29 +167,29 @@ __global__ __launch_bounds__(256) void tile_splits_kernel(TileArgs<K> P, int64_t
     if constexpr (G == 1) return split_search<int64_t>(d, lo, hi, ga, gb);
     else return group_split_search<G, int64_t>(d, lo, hi, ga, gb);
   };
-  if constexpr (KIND == kTileExplicit) {
-    // k is a tile: its start inside its own pair, and the end of the tile
-    // before it in the same pair; the pair's last tile also gets the pair end
-    if (k >= P.tile_off[P.n_pairs]) return;  // a group exits as one
-    const int64_t pk = P.tile_pair[k], j = k - P.tile_off[pk];
-    int64_t a0, a1, b0, b1;
-    batch_pair(P, pk, a0, a1, b0, b1);
-    const int64_t size = (a1 - a0) + (b1 - b0), dl = j * T;
-    int64_t lo, hi;
-    diag_range<int64_t>(dl, a1 - a0, b1 - b0, lo, hi);
-    const K *A = P.A + a0, *B = P.B + b0;
-    const int64_t a = j == 0 ? 0 : search(dl, lo, hi, [&](int64_t i) { return A[i]; },
-                                          [&](int64_t q) { return B[q]; });
+  if constexpr (KIND == kTileBatch) {
+    // boundary k: the global split on diagonal min(kT, N), found in the
+    // pair holding output kT
+    if (k > P.n_tiles) return;  // a group exits as one
+    const int64_t D = k * T < P.N ? k * T : P.N;
+    int64_t a = P.NA;
+    if (D < P.N) {
+      int64_t pk = P.tile_pair[k];
+      pk = pk < 0 ? 0 : (pk >= P.n_pairs ? P.n_pairs - 1 : pk);
+      int64_t a0, a1, b0, b1;
+      batch_pair(P, pk, a0, a1, b0, b1);
+      const int64_t size = (a1 - a0) + (b1 - b0);
+      int64_t dl = D - (a0 + b0);
+      dl = dl < 0 ? 0 : (dl > size ? size : dl);
+      int64_t lo, hi;
+      diag_range<int64_t>(dl, a1 - a0, b1 - b0, lo, hi);
+      const K *A = P.A + a0, *B = P.B + b0;
+      a = a0 + search(dl, lo, hi, [&](int64_t i) { return A[i]; }, [&](int64_t q) { return B[q]; });
+    }
     if constexpr (G > 1) {
       if ((threadIdx.x & (G - 1)) != 0) return;
     }
-    const int64_t out = a0 + b0;
-    const int64_t n = size - dl < T ? size - dl : T;
-    if (n * (int64_t)sizeof(K) >= kTileHdrBytes) {
-      put_tile_hdr(P.S, out + dl, 0, a0 + a, b0 + (dl - a));
-      if (dl + T >= size) put_tile_hdr(P.S, out + dl, 1, a1, b1);
-    }
-    if (j > 0) put_tile_hdr(P.S, out + dl - T, 1, a0 + a, b0 + (dl - a));  // full tile
+    P.split_out[k] = a;
     return;
   } else {
   if (k > P.n_tiles) return;  // a group exits as one (G divides 256)
@@ -253,20 +242,18 @@ __global__ __launch_bounds__(256) void tile_splits_kernel(TileArgs<K> P, int64_t
 
 // Chunk of CH elements at src + g: one vector access when the chunk lies
 // inside the array (lim elements), element loads for the part inside else.
-// NTL: nontemporal loads, for windows read once in long streams (single
-// merges, sort rounds); a batch's small tiles share their edge lines with
-// the neighbouring pairs and keep ordinary loads.
-template <typename T, int CH, bool NTL>
+// Vector loads are nontemporal: every window is read once, in long streams.
+template <typename T, int CH>
 __device__ __forceinline__ void tile_load_chunk(const T *__restrict__ src, int64_t g, int64_t lim,
                                                 T (&v)[CH]) {
   typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
   if (g + CH <= lim) {
     if constexpr (CH * sizeof(T) == 16) {
       const u32x4 *p = reinterpret_cast<const u32x4 *>(src + g);
-      *reinterpret_cast<u32x4 *>(v) = NTL ? __builtin_nontemporal_load(p) : *p;
+      *reinterpret_cast<u32x4 *>(v) = __builtin_nontemporal_load(p);
     } else if constexpr (CH * sizeof(T) == 8) {
       const u32x2 *p = reinterpret_cast<const u32x2 *>(src + g);
-      *reinterpret_cast<u32x2 *>(v) = NTL ? __builtin_nontemporal_load(p) : *p;
+      *reinterpret_cast<u32x2 *>(v) = __builtin_nontemporal_load(p);
     } else {
 #pragma unroll
       for (int i = 0; i < CH; ++i) v[i] = src[g + i];
@@ -315,6 +302,44 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t b, int64_t G) {
   return x * q + (x < r ? x : r) + i;
 }
 
+// Serial merge of VT outputs of a batch tile for a lane whose outputs cross
+// the end of its pair.  A pair's part of the tile is the merge of its parts
+// of the two windows; where the lane's part ends (seg, the outputs left in
+// it, reaches 0) next(cur, ...) moves it to the part holding tile output cur,
+// which starts where the finished parts ended, and returns that part's LDS
+// positions, limits and length.  Outputs at or past the tile's end n are
+// discarded by the caller.
+template <typename K, int VT, typename Next>
+__device__ __forceinline__ void merge_lane_parts(const K *keys, int ai, int bi, int a_end,
+                                                 int b_end, int seg, int cur, int n, Next next,
+                                                 K (&out)[VT]) {
+  K ka = keys[ai];
+  K kb = keys[bi];
+#pragma unroll
+  for (int i = 0; i < VT; ++i) {
+    if (seg <= 0 && cur < n) {
+      next(cur, ai, bi, a_end, b_end, seg);
+      ka = keys[ai];
+      kb = keys[bi];
+    }
+    const bool take_b = (bi < b_end) && (ai >= a_end || kb < ka);
+    out[i] = take_b ? kb : ka;
+    const int taken = take_b ? bi : ai;
+    ai = take_b ? ai : taken + 1;
+    bi = take_b ? taken + 1 : bi;
+    const K nxt = keys[taken + 1];
+    ka = take_b ? ka : nxt;
+    kb = take_b ? nxt : kb;
+    --seg;
+    ++cur;
+  }
+}
+
+// A batch tile keeps the starts of its pairs relative to its windows in LDS
+// when it spans fewer than kPairTab of them (else lanes look pairs up in
+// global memory).
+constexpr int kPairTab = 256;
+
 // Step 2.  One workgroup per tile.
 template <typename K, bool KV, int NT, int VT, int KIND, int SRC, bool VLOAD>
 __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
@@ -322,44 +347,39 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
   constexpr int T = L::T, CH = L::CH;
   __shared__ __attribute__((aligned(16))) K keys[L::N_KEYS];
   __shared__ __attribute__((aligned(16))) uint32_t vals[L::N_VALS];
+  // kTileBatch: window-relative starts of the tile's pairs
+  __shared__ int32_t tab_a[KIND == kTileBatch ? kPairTab : 1];
+  __shared__ int32_t tab_b[KIND == kTileBatch ? kPairTab : 1];
   const int tid = threadIdx.x;
-  // (a batch's grid covers an upper bound of its tiles, and its tiles are
-  // short and of uneven length: plain order measured 4% faster there)
-  int64_t tile;
-  if constexpr (KIND == kTileExplicit) {
-    tile = blockIdx.x;
-    if (tile >= P.tile_off[P.n_pairs]) return;  // past the batch's tiles
-  } else {
-    tile = tile_of_block(blockIdx.x, gridDim.x);
-  }
+  const int64_t tile = tile_of_block(blockIdx.x, gridDim.x);
   const int64_t N = P.N, NA = P.NA, NB = P.NB;
   // output range of the tile, and for a header-less tile the pair it ends
   // ([alo, ia) of A and [blo, ib) of B)
-  int64_t d0;
-  int n;
+  const int64_t d0 = tile * T;
+  const int n = (int)(N - d0 < T ? N - d0 : T);
   int64_t alo = 0, blo = 0, ia = NA, ib = NB;
-  if constexpr (KIND == kTileExplicit) {
-    const int64_t pk = P.tile_pair[tile], j = tile - P.tile_off[pk];
-    batch_pair(P, pk, alo, ia, blo, ib);
-    const int64_t rest = (ia - alo) + (ib - blo) - j * T;
-    d0 = alo + blo + j * T;
-    n = (int)(rest < T ? rest : T);
-    if (n <= 0) return;  // (only for inconsistent workspace contents)
-  } else {
-    d0 = tile * T;
-    n = (int)(N - d0 < T ? N - d0 : T);
-    if constexpr (KIND == kTileRuns) {
-      int64_t P0, aE, bE;
-      run_pair(d0, N, P.lw, P0, aE, bE);
-      alo = P0;
-      blo = aE;
-      ia = aE;
-      ib = bE;
-    }
+  if constexpr (KIND == kTileRuns) {
+    int64_t P0, aE, bE;
+    run_pair(d0, N, P.lw, P0, aE, bE);
+    alo = P0;
+    blo = aE;
+    ia = aE;
+    ib = bE;
   }
 
   // ---- the tile's pair --------------------------------------------------
   int64_t a0, b0, a1;
+  // kTileBatch: the pairs holding the tile's first output (pf) and the next
+  // tile's (pn); the table covers pairs pf .. pn + 1 (cnt entries)
+  int64_t pf = 0, cnt = 0;
+  if constexpr (KIND == kTileBatch) {
+    pf = P.tile_pair[tile];
+    int64_t pn = tile + 1 < P.n_tiles ? (int64_t)P.tile_pair[tile + 1] : P.n_pairs - 1;
+    pf = pf < 0 ? 0 : (pf >= P.n_pairs ? P.n_pairs - 1 : pf);
+    pn = pn < pf ? pf : (pn >= P.n_pairs ? P.n_pairs - 1 : pn);
+    cnt = pn + 2 - pf;
+  }
+  const bool use_tab = KIND == kTileBatch && cnt <= kPairTab;
   if constexpr (SRC == kTileSplitArray) {
     // the caller's splits: a0 kept on the start diagonal inside the grid and
     // the A count in its valid range, whatever the values (for the true
@@ -375,7 +395,7 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
     b0 = (int64_t)(((uint64_t)h[3] << 32) | h[2]);
     a1 = (int64_t)(((uint64_t)h[5] << 32) | h[4]);
   } else {
-    // last tile (of the grid, run pair or batch pair), shorter than a
+    // last tile (of the grid or of a run pair), shorter than a
     // header: from that end step the path back n times; each step takes the
     // larger of the two keys before the cursor, B on ties (ties went to A
     // forwards)
@@ -407,6 +427,7 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
   const int ca = (sa + wa + CH - 1) / CH, cb = (sb + wb + CH - 1) / CH;
   const int64_t abase = a0 - sa, bbase = b0 - sb;
   const int pa = sa, pb = ca * CH + sb;  // LDS positions of A[a0] and B[b0]
+  int64_t lp = 0, lp_a = 0, lp_b = 0, lp_a1 = 0, lp_b1 = 0;  // kTileBatch: lane's pair
   {
     constexpr int PV = (T / CH + 4 + NT - 1) / NT;
     K rk[PV][CH];
@@ -418,9 +439,38 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
         const bool fb = c >= ca;
         const int64_t g = fb ? bbase + (int64_t)(c - ca) * CH : abase + (int64_t)c * CH;
         const int64_t lim = fb ? NB : NA;
-        constexpr bool NTL = KIND != kTileExplicit;
-        tile_load_chunk<K, CH, NTL>(fb ? P.B : P.A, g, lim, rk[k]);
-        if constexpr (KV) tile_load_chunk<uint32_t, CH, NTL>(fb ? P.Bv : P.Av, g, lim, rv[k]);
+        tile_load_chunk<K, CH>(fb ? P.B : P.A, g, lim, rk[k]);
+        if constexpr (KV) tile_load_chunk<uint32_t, CH>(fb ? P.Bv : P.Av, g, lim, rv[k]);
+      }
+    }
+    // kTileBatch: the pair starts for the table (their loads go out with
+    // the window loads), else the lane's own pair from global memory
+    constexpr int TPL = KIND == kTileBatch ? (kPairTab + NT - 1) / NT : 1;
+    int64_t ta[TPL], tb[TPL];
+    if constexpr (KIND == kTileBatch) {
+      if (use_tab) {
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+          const int i = tid + k * NT;
+          if (i < cnt) {
+            ta[k] = batch_a_at(P, pf + i);
+            tb[k] = batch_b_at(P, pf + i);
+          }
+        }
+      } else {
+        const int dl0 = tid * VT < n ? tid * VT : n;
+        lp = pf;
+        lp_a = batch_a_at(P, pf);
+        lp_b = batch_b_at(P, pf);
+        lp_a1 = batch_a_at(P, pf + 1);
+        lp_b1 = batch_b_at(P, pf + 1);
+        if (dl0 < n && lp_a1 + lp_b1 <= d0 + dl0) {
+          lp = batch_pair_of(P, pf, d0 + dl0);
+          lp_a = batch_a_at(P, lp);
+          lp_b = batch_b_at(P, lp);
+          lp_a1 = batch_a_at(P, lp + 1);
+          lp_b1 = batch_b_at(P, lp + 1);
+        }
       }
     }
 #pragma unroll
@@ -431,19 +481,104 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
         if constexpr (KV) tile_put_chunk<uint32_t, CH>(vals + c * CH, rv[k]);
       }
     }
+    if constexpr (KIND == kTileBatch) {
+      if (use_tab) {
+        // starts relative to the windows, kept inside them (a pair that
+        // starts before the tile reads as 0, one after it as its end)
+#pragma unroll
+        for (int k = 0; k < TPL; ++k) {
+          const int i = tid + k * NT;
+          if (i < cnt) {
+            const int64_t ra = ta[k] - a0, rb = tb[k] - b0;
+            tab_a[i] = (int32_t)(ra < 0 ? 0 : (ra > wa ? wa : ra));
+            tab_b[i] = (int32_t)(rb < 0 ? 0 : (rb > wb ? wb : rb));
+          }
+        }
+      }
+    }
   }
   __syncthreads();
 
   // ---- lane split and serial merge ---------------------------------------
   const int dl = tid * VT < n ? tid * VT : n;
-  int lo, hi;
-  diag_range<int>(dl, wa, wb, lo, hi);
-  const int a = split_search<int>(
-      dl, lo, hi, [&](int i) { return keys[pa + i]; }, [&](int j) { return keys[pb + j]; });
   const int steps = n - dl < VT ? n - dl : VT;
   K out[VT];
   int src[VT];
-  serial_merge<K, VT>(keys, pa + a, pb + (dl - a), pa + wa, pb + wb, out, src);
+  if constexpr (KIND == kTileBatch) {
+    // the lane's pair's parts of the windows (LDS offsets from pa and pb)
+    // and its split there: the pair's part of the tile is the merge of
+    // those parts (Theorem 5)
+    auto cl = [](int64_t v, int64_t lo_, int64_t hi_) {
+      return (int)(v < lo_ ? lo_ : (v > hi_ ? hi_ : v));
+    };
+    int pa_lo, pa_hi, pb_lo, pb_hi, seg;
+    int ti = 0;  // table entry of the lane's pair
+    if (use_tab) {
+      // last entry (before the final one) whose pair starts at or before dl
+      int lo_ = 0, hi_ = (int)cnt - 1;
+      while (lo_ + 1 < hi_) {
+        const int mid = (lo_ + hi_) >> 1;
+        if (tab_a[mid] + tab_b[mid] <= dl) lo_ = mid; else hi_ = mid;
+      }
+      ti = lo_;
+      pa_lo = tab_a[ti];
+      pb_lo = tab_b[ti];
+      pa_hi = tab_a[ti + 1] > pa_lo ? tab_a[ti + 1] : pa_lo;
+      pb_hi = tab_b[ti + 1] > pb_lo ? tab_b[ti + 1] : pb_lo;
+      seg = tab_a[ti + 1] + tab_b[ti + 1] - dl;
+    } else {
+      pa_lo = cl(lp_a - a0, 0, wa);
+      pa_hi = cl(lp_a1 - a0, pa_lo, wa);
+      pb_lo = cl(lp_b - b0, 0, wb);
+      pb_hi = cl(lp_b1 - b0, pb_lo, wb);
+      seg = cl(lp_a1 + lp_b1 - (d0 + dl), -1, T + 1);
+    }
+    const int na_p = pa_hi - pa_lo, nb_p = pb_hi - pb_lo;
+    int dlp = dl - (pa_lo + pb_lo < dl ? pa_lo + pb_lo : dl);
+    dlp = dlp < na_p + nb_p ? dlp : na_p + nb_p;
+    int lo, hi;
+    diag_range<int>(dlp, na_p, nb_p, lo, hi);
+    const int a = split_search<int>(
+        dlp, lo, hi, [&](int i) { return keys[pa + pa_lo + i]; },
+        [&](int j) { return keys[pb + pb_lo + j]; });
+    const int ai = pa + pa_lo + a, bi = pb + pb_lo + (dlp - a);
+    if (seg >= steps) {
+      serial_merge<K, VT>(keys, ai, bi, pa + pa_hi, pb + pb_hi, out, src);
+    } else if (use_tab) {
+      merge_lane_parts<K, VT>(
+          keys, ai, bi, pa + pa_hi, pb + pb_hi, seg, dl, n,
+          [&](int cur, int &ai_, int &bi_, int &ae, int &be, int &sg) {
+            while (ti + 2 < cnt && tab_a[ti + 1] + tab_b[ti + 1] <= cur) ++ti;
+            const int a_lo = tab_a[ti], b_lo = tab_b[ti];
+            ai_ = pa + a_lo;
+            bi_ = pb + b_lo;
+            ae = pa + (tab_a[ti + 1] > a_lo ? tab_a[ti + 1] : a_lo);
+            be = pb + (tab_b[ti + 1] > b_lo ? tab_b[ti + 1] : b_lo);
+            sg = tab_a[ti + 1] + tab_b[ti + 1] - cur;
+          },
+          out);
+    } else {
+      merge_lane_parts<K, VT>(
+          keys, ai, bi, pa + pa_hi, pb + pb_hi, seg, dl, n,
+          [&](int cur, int &ai_, int &bi_, int &ae, int &be, int &sg) {
+            lp = batch_pair_of(P, lp, d0 + cur);
+            const int64_t ga = batch_a_at(P, lp), gb = batch_b_at(P, lp);
+            const int64_t ga1 = batch_a_at(P, lp + 1), gb1 = batch_b_at(P, lp + 1);
+            ai_ = pa + cl(ga - a0, 0, wa);
+            bi_ = pb + cl(gb - b0, 0, wb);
+            ae = pa + cl(ga1 - a0, ai_ - pa, wa);
+            be = pb + cl(gb1 - b0, bi_ - pb, wb);
+            sg = cl(ga1 + gb1 - (d0 + cur), -1, T + 1);
+          },
+          out);
+    }
+  } else {
+    int lo, hi;
+    diag_range<int>(dl, wa, wb, lo, hi);
+    const int a = split_search<int>(
+        dl, lo, hi, [&](int i) { return keys[pa + i]; }, [&](int j) { return keys[pb + j]; });
+    serial_merge<K, VT>(keys, pa + a, pb + (dl - a), pa + wa, pb + wb, out, src);
+  }
   uint32_t ov[KV ? VT : 1];
   if constexpr (KV) {
     // (past a short lane's run, src may point beyond the staged values)
@@ -508,8 +643,8 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
 
 template <typename K, int KIND>
 static hipError_t launch_tile_splits(const TileArgs<K> &P, int64_t T, hipStream_t s) {
-  // boundaries 0 .. n_tiles, or for a batch one item per (possible) tile
-  const int64_t n_b = KIND == kTileExplicit ? P.n_tiles : P.n_tiles + 1;
+  // boundaries 0 .. n_tiles
+  const int64_t n_b = P.n_tiles + 1;
   const int g = partition_lanes(n_b);
   const int64_t blocks = (n_b * g + 255) / 256;
   switch (g) {
@@ -540,22 +675,18 @@ static hipError_t launch_tiles_shape(TileArgs<K> P, bool vload, hipStream_t s) {
     constexpr int64_t T = (int64_t)NT * VT;
     P.n_tiles = (P.N + T - 1) / T;
     if (P.n_tiles == 0) return hipSuccess;
-    if constexpr (KIND == kTileExplicit) {
-      // tiles per pair, scanned into the workspace
-      P.n_tiles += P.n_pairs;
-      const int64_t n_blocks = (P.n_pairs + kBatchPairsPerBlock - 1) / kBatchPairsPerBlock;
-      P.bsum = P.tile_off + (P.n_pairs + 1);
-      P.tile_pair = reinterpret_cast<int32_t *>(P.bsum + n_blocks);
+    if constexpr (KIND == kTileBatch) {
+      // workspace: the splits (n_tiles + 1 int64), then the pair of every
+      // tile's first output (n_tiles int32)
+      P.a_split = P.split_out;
+      P.tile_pair = reinterpret_cast<int32_t *>(P.split_out + P.n_tiles + 1);
       KernelTimer timer("batch_tiles", s);
-      hipLaunchKernelGGL((batch_count_kernel<K>), dim3((unsigned)n_blocks), dim3(kBatchLanes), 0, s,
-                         P, T);
-      hipLaunchKernelGGL((batch_sums_kernel<K>), dim3(1), dim3(kBatchLanes), 0, s, P, n_blocks);
-      hipLaunchKernelGGL((batch_fill_kernel<K>), dim3((unsigned)n_blocks), dim3(kBatchLanes), 0, s,
-                         P, T);
+      hipLaunchKernelGGL((batch_bound_kernel<K>), dim3((unsigned)((P.n_pairs + 255) / 256)), dim3(256),
+                         0, s, P, T);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    if constexpr (SRC == kTileHeader) {
+    if constexpr (SRC == kTileHeader || KIND == kTileBatch) {
       KernelTimer timer("tile_splits", s);
       const hipError_t e = launch_tile_splits<K, KIND>(P, T, s);
       if (e != hipSuccess) return e;
@@ -574,7 +705,7 @@ static hipError_t launch_tiles_shape(TileArgs<K> P, bool vload, hipStream_t s) {
 template <typename K, int KIND, int SRC>
 static hipError_t launch_tiles_any(TileCfg cfg, const TileArgs<K> &P, bool vload, hipStream_t s) {
   // (merges on given splits and batches carry keys only)
-  constexpr bool KV_OK = SRC == kTileHeader && KIND != kTileExplicit;
+  constexpr bool KV_OK = SRC == kTileHeader && KIND != kTileBatch;
   const bool kv = KV_OK && P.Sv != nullptr;
 #define MP_TILE_CASE(NT_, VT_)                                                             \
   if (cfg.nt == NT_ && cfg.vt == VT_) {                                                    \
@@ -629,9 +760,9 @@ hipError_t launch_merge_batched_tiles(TileCfg cfg, const K *A, const int64_t *a_
   P.A = A; P.B = B; P.S = S;
   P.NA = total_a; P.NB = total_b; P.N = total_a + total_b;
   P.a_off = a_off; P.b_off = b_off; P.n_pairs = n_pairs;
-  P.tile_off = reinterpret_cast<int64_t *>(ws);
+  P.split_out = reinterpret_cast<int64_t *>(ws);
   const bool vload = tile_aligned16(A) && tile_aligned16(B);
-  return launch_tiles_any<K, kTileExplicit, kTileHeader>(cfg, P, vload, s);
+  return launch_tiles_any<K, kTileBatch, kTileSplitArray>(cfg, P, vload, s);
 }
 
 template <typename K>

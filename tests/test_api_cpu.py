@@ -173,7 +173,7 @@ def test_sort_and_batched_argument_errors(L):
     assert L.mp_merge_batched(MP_I32, a, None, b, bo, 3, 5, 5, s, None, 0, None) == INVALID
     assert L.mp_merge_batched(MP_I32, a, ao, b, bo, 3, 5, 5, P(0x10000 + 8), None, 0, None) == OVERLAP
     assert L.mp_merge_batched(MP_I32, None, None, None, None, 0, 0, 0, None, None, 0, None) == OK
-    # per-pair tiles (mean pair >= 1024 keys) need the workspace
+    # batch tiles need the workspace
     a2, b2, s2, w2 = P(0x100000), P(0x200000), P(0x300000), P(0x400000)
     need = L.mp_merge_batched_workspace_bytes(MP_I32, 1, 4000)
     assert need > 0

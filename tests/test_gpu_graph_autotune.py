@@ -67,16 +67,18 @@ def test_graph_batched_replays_match_eager(mp, orc):
     want = orc.merge_batched(A, a_off, B, b_off)
     dA, dB, da, db = dev(A), dev(B), dev(a_off), dev(b_off)
     out = torch.empty(len(A) + len(B), dtype=torch.int32, device="cuda")
+    ws = torch.empty(mp.merge_batched_workspace_bytes(torch.int32, len(a_off) - 1, len(out)),
+                     dtype=torch.uint8, device="cuda")
     mp.graph_clear()
     mp.graph_mode(True)
     try:
         for rep in range(3):
             out.fill_(0)
-            mp.merge_batched(dA, da, dB, db, out=out)
+            mp.merge_batched(dA, da, dB, db, out=out, ws=ws)
             assert host(out).tobytes() == want.tobytes(), rep
         assert mp.graph_count() == 1
         out2 = torch.empty_like(out)          # new output pointer -> a second graph
-        mp.merge_batched(dA, da, dB, db, out=out2)
+        mp.merge_batched(dA, da, dB, db, out=out2, ws=ws)
         assert host(out2).tobytes() == want.tobytes()
         assert mp.graph_count() == 2
     finally:

@@ -232,22 +232,31 @@ def test_sort_guards(mp, orc, dt, kv):
         assert first_mismatch(kbuf.host(), orc.sort(keys)) is None
 
 
-def test_batched_guards(mp, orc):
+@pytest.mark.parametrize("path", ["built_in", "persistent"])
+def test_batched_guards(mp, orc, path):
+    """Batched merge (built-in batch tiles, and the persistent kernel whose
+    workgroups walk several tiles) into a guarded output, two fills."""
     from gpu_util import dev, first_mismatch
     A, a_off, B, b_off = gen.batched_pairs(3000, 108, median=700.0)
     want = orc.merge_batched(A, a_off, B, b_off)
     out = Guarded(len(A) + len(B), _torch_dtype(np.int32), FILLS[0])
     dA, dB, da, db = dev(A), dev(B), dev(a_off), dev(b_off)
-    for fill in FILLS:
-        out.refill(fill)
-        mp.timing_enable(True)
-        mp.merge_batched(dA, da, dB, db, out=out.view)
-        tiles, _ = mp.stats_query()
-        groups = mp.stats_workgroups()
-        mp.timing_enable(False)
-        assert out.guards_intact()
-        assert first_mismatch(out.host(), want) is None, fill
-        assert tiles >= groups > 0
+    if path == "persistent":
+        mp.set_config("batched", 2, 256, 16)
+    try:
+        for fill in FILLS:
+            out.refill(fill)
+            mp.timing_enable(True)
+            mp.merge_batched(dA, da, dB, db, out=out.view)
+            tiles, _ = mp.stats_query()
+            groups = mp.stats_workgroups()
+            mp.timing_enable(False)
+            assert out.guards_intact()
+            assert first_mismatch(out.host(), want) is None, fill
+            if path == "persistent":
+                assert tiles >= groups > 0
+    finally:
+        mp.set_config("batched", None)
 
 
 @pytest.mark.parametrize("op", ["intersection", "union", "difference", "symmetric_difference"])
@@ -322,10 +331,9 @@ def test_set_op_unsorted_inputs_stay_inside_s(mp, op):
 
 
 def _batch_edge_pairs(T, seed):
-    """Pair sizes that meet every edge of the per-pair tiles of T outputs:
-    empty pairs (runs of them), one-sided pairs, sizes just under, at and
-    just over multiples of T (last tiles of 1..7 keys, too short for a
-    header), and lognormal bulk."""
+    """Pair sizes that meet every edge of tiles of T outputs: empty pairs
+    (runs of them), one-sided pairs, sizes just under, at and just over
+    multiples of T, tiny pairs, and lognormal bulk."""
     g = np.random.default_rng(seed)
     sizes = [0, 0, 0, T, T - 1, T + 1, 2 * T, 2 * T + 3, 3 * T + 7, 1, 2, 7, 8, 9, 5 * T + 5]
     sizes += list(np.clip(np.rint(g.lognormal(np.log(0.7 * T), 0.8, 300)), 0, 8 * T).astype(int))
@@ -350,7 +358,7 @@ def _batch_edge_pairs(T, seed):
 
 @pytest.mark.parametrize("shape", [(256, 8), (256, 16), (512, 16), (1024, 8), (1024, 16)])
 def test_batched_per_pair_tiles(mp, orc, shape):
-    """Batches through per-pair tiles (mode 1), every tile shape, against the
+    """Batches through batch tiles (mode 1), every tile shape, against the
     oracle, with guard canaries and two fills."""
     from gpu_util import dev, first_mismatch
     nt, vt = shape
@@ -374,9 +382,41 @@ def test_batched_per_pair_tiles(mp, orc, shape):
         mp.set_config("batched", None)
 
 
+@pytest.mark.parametrize("shape", [(256, 8), (256, 16), (1024, 16)])
+@pytest.mark.parametrize("hi", [6, 40])
+def test_batched_tiles_tiny_pairs(mp, orc, shape, hi):
+    """Tiles over batches of short pairs (0 to 5 or 0 to 39 keys, runs of
+    empty pairs, pairs of exactly one lane's outputs), so that many lanes'
+    outputs cross one or more pair ends; tiles spanning fewer or more pairs
+    than their LDS pair table holds; against the oracle with guards."""
+    from gpu_util import dev, first_mismatch
+    nt, vt = shape
+    g = np.random.default_rng(130 + vt + hi)
+    sizes = list(g.integers(0, hi, 20000)) + [0] * 500 + [vt] * 300 + [2 * vt + 1] * 50
+    sizes += list(g.integers(0, 3, 5000)) + [nt * vt + 1, 1, 0, 0, 3]
+    na = np.array([int(g.integers(0, s + 1)) for s in sizes], np.int64)
+    nb = np.array(sizes, np.int64) - na
+    A = np.concatenate([np.sort(g.integers(0, 8, k)).astype(np.int32) for k in na])
+    B = np.concatenate([np.sort(g.integers(0, 8, k)).astype(np.int32) for k in nb])
+    a_off, b_off = gen.offsets(na), gen.offsets(nb)
+    want = orc.merge_batched(A, a_off, B, b_off)
+    out = Guarded(len(A) + len(B), torch.int32, FILLS[0])
+    need = mp.merge_batched_workspace_bytes(torch.int32, len(sizes), len(A) + len(B))
+    ws = Guarded(need, torch.uint8, FILLS[1])
+    mp.set_config("batched", 1, nt, vt)
+    try:
+        for fill in FILLS:
+            out.refill(fill)
+            mp.merge_batched(dev(A), dev(a_off), dev(B), dev(b_off), out=out.view, ws=ws.view)
+            assert out.guards_intact() and ws.guards_intact()
+            assert first_mismatch(out.host(), want) is None, (shape, fill)
+    finally:
+        mp.set_config("batched", None)
+
+
 def test_batched_built_in_choice(mp, orc):
-    """The built-in batch configuration: per-pair tiles for a batch of long
-    pairs, the persistent kernel for a batch of short ones; both exact."""
+    """The built-in batch configuration (batch tiles) on a batch of long
+    pairs and on one of short pairs; both exact."""
     from gpu_util import dev, first_mismatch
     for median in (6000.0, 40.0):
         A, a_off, B, b_off = gen.batched_pairs(2000, 121, median=median)

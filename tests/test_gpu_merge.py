@@ -119,6 +119,11 @@ def test_merge_split_from_partition(mp, orc, tile):
         d = _tile_diagonals(n, tile)
         dA, dB = dev(A), dev(B)
         sp = mp.partition(dA, dB, dev(d))
+        if tile * A.itemsize > 64 * 1024:
+            # a tile of 8-byte keys that would need 128 KiB of LDS is not built
+            with pytest.raises(mp.MergePathError, match="MP_ERR_UNSUPPORTED"):
+                mp.merge_split(dA, dB, sp, tile)
+            continue
         got = host(mp.merge_split(dA, dB, sp, tile))
         assert first_mismatch(got, orc.merge(A, B)) is None, (A.dtype, len(A), len(B))
 
