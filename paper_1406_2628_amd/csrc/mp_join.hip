@@ -8,20 +8,24 @@
 //    in the merge (Theorem 17 for the lanes' splits, Lemma 1 for the walk).
 //    When the walk takes A[i] its column b is the first B position whose key
 //    is not below A[i] (ties take A first), so B's copies of A[i] are
-//    B[b, b + c); c is read off the B window (a search in LDS), and only a
-//    run that reaches the window's end continues in global memory.  Each A
-//    key gets lo[i] = b and c[i] = c.
+//    B[b, b + c).  The walk records b per A key in LDS; then the first key
+//    of every run of equal A keys reads c off the B window (a gallop in
+//    LDS), and only the one value whose B run reaches past the window's end
+//    continues in global memory.  Each A key gets lo[i] = b and c[i] = c,
+//    written by consecutive lanes for consecutive keys.
 // 2. Offsets: an exclusive scan of c over A gives each A key the position of
 //    its first pair, and the total, which goes to *count.
 // 3. Pairs (join_emit_kernel), balanced whatever the duplicates: output p
 //    belongs to the last A key i with off[i] <= p.  That is again a merge:
 //    of off[] (non-decreasing) with the output indices 0, 1, 2, ..., ties
 //    taking off[] first, and output p then lies in the rows of key i at
-//    column p - off[i].  So the emission is the Merge Path merge of those two
-//    sequences: tiles of E items of the combined grid (keys and pairs
-//    together) split by Algorithm 2, each lane walking E / NT items.  The
-//    number of tiles is only known on the device (it depends on the count),
-//    so a grid of resident workgroups walks them.
+//    column p - off[i].  So the emission is cut like a Merge Path merge of
+//    those two sequences: tiles of E items of the combined grid (keys and
+//    pairs together) split by Algorithm 2.  Inside a tile, consecutive lanes
+//    take consecutive outputs and find their key by a search over the
+//    tile's offsets in LDS, so the pairs are stored coalesced.  The number
+//    of tiles is only known on the device (it depends on the count), so a
+//    grid of resident workgroups walks them.
 #include <stdint.h>
 
 #include "mp_device.h"
@@ -31,8 +35,8 @@ namespace mp {
 
 namespace {
 
-constexpr int kJoinNT = 256, kJoinVT = 16, kJoinT = kJoinNT * kJoinVT;  // rank tiles
-constexpr int kEmitNT = 256, kEmitVT = 8, kEmitE = kEmitNT * kEmitVT;     // emission tiles
+constexpr int kJoinNT = 256, kJoinVT = 8, kJoinT = kJoinNT * kJoinVT;   // rank tiles
+constexpr int kEmitNT = 256, kEmitE = 2048;                               // emission tiles
 constexpr int kScanPer = 4;                                              // keys per scan lane
 constexpr int64_t kScanBlock = 1024 * kScanPer;
 
@@ -67,6 +71,9 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
     int64_t *__restrict__ cnt_out) {
   constexpr int NT = kJoinNT, VT = kJoinVT, T = kJoinT;
   __shared__ K keys[T + VT + 1];
+  __shared__ int32_t s_lo[T];   // per A key of the window: first B column, from b0
+  __shared__ int32_t s_cnt[T];  // per run head: B run length in the window, -1 past it
+  __shared__ int64_t s_big;     // the B run length of the value that goes past it
   const int tid = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t N = na + nb;
@@ -97,60 +104,87 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
       if (i < n) keys[i] = r[s];
     }
   }
+  if (tid == 0) s_big = 0;
   __syncthreads();
-  const int dl = tid * VT < n ? tid * VT : n;
-  int lo, hi;
-  diag_range<int>(dl, wa, wb, lo, hi);
-  const int a = split_search<int>(
-      dl, lo, hi, [&](int i) { return keys[i]; }, [&](int j) { return keys[wa + j]; });
-  int ai = a, bi = wa + (dl - a);
-  const int steps = n - dl < VT ? n - dl : VT;
-  bool have = false;  // this lane's last distinct A key and its run
-  K last{};
-  int64_t last_lo = 0, last_cnt = 0;
-  for (int s = 0; s < steps; ++s) {
-    const bool take_b = (bi < n) && (ai >= wa || keys[bi] < keys[ai]);
-    if (take_b) {
-      ++bi;
-      continue;
-    }
-    const K v = keys[ai];
-    const int64_t col = b0 + (bi - wa);  // first B position not below v
-    if (!have || !key_equal(v, last) || col != last_lo) {
-      int64_t c = 0;
-      if (bi < n) {
-        if (key_equal(keys[bi], v)) {
-          // B run of v inside the window: upper bound in LDS
-          int l = bi, h = n;
-          while (l < h) {
-            const int m = (l + h) >> 1;
-            if (v < keys[m]) h = m; else l = m + 1;
-          }
-          c = l - bi;
-          if (l == n) c += upper_from(B, b1, nb, v) - b1;  // run goes on past the window
-        }
-      } else if (b1 < nb && key_equal(B[b1], v)) {
-        c = upper_from(B, b1, nb, v) - b1;
+  // the walk: each A key's first B column (ties take A, so every B key
+  // before it is smaller)
+  {
+    const int dl = tid * VT < n ? tid * VT : n;
+    int lo, hi;
+    diag_range<int>(dl, wa, wb, lo, hi);
+    const int a = split_search<int>(
+        dl, lo, hi, [&](int i) { return keys[i]; }, [&](int j) { return keys[wa + j]; });
+    int ai = a, bi = wa + (dl - a);
+    const int steps = n - dl < VT ? n - dl : VT;
+    K ka = keys[ai], kb = keys[bi];
+#pragma unroll
+    for (int s = 0; s < VT; ++s) {
+      if (s < steps) {
+        const bool take_b = (bi < n) && (ai >= wa || kb < ka);
+        if (!take_b && ai < wa) s_lo[ai] = bi - wa;
+        const int taken = take_b ? bi : ai;
+        ai = take_b ? ai : taken + 1;
+        bi = take_b ? taken + 1 : bi;
+        const K nxt = keys[taken + 1];
+        ka = take_b ? ka : nxt;
+        kb = take_b ? nxt : kb;
       }
-      have = true;
-      last = v;
-      last_lo = col;
-      last_cnt = c;
     }
-    lo_out[a0 + ai] = last_lo;
-    cnt_out[a0 + ai] = last_cnt;
-    ++ai;
+  }
+  __syncthreads();
+  // run heads: the length of the B run of their value, galloping in the
+  // window from the first column; only the value equal to the window's last
+  // B key can go on past it
+  for (int i = tid; i < wa; i += NT) {
+    const K v = keys[i];
+    if (i > 0 && key_equal(keys[i - 1], v)) continue;
+    const int j0 = wa + (s_lo[i] < 0 ? 0 : (s_lo[i] > wb ? wb : s_lo[i]));
+    int l = j0;
+    if (j0 < n && key_equal(keys[j0], v)) {
+      int base = j0, step = 1;
+      while (base + step < n && key_equal(keys[base + step], v)) {
+        base += step;
+        step <<= 1;
+      }
+      int lo2 = base + 1, hi2 = base + step < n ? base + step : n;
+      while (lo2 < hi2) {
+        const int m = (lo2 + hi2) >> 1;
+        if (key_equal(keys[m], v)) lo2 = m + 1; else hi2 = m;
+      }
+      l = lo2;
+    }
+    int c = l - j0;
+    if (l == n && b1 < nb && key_equal(B[b1], v)) {
+      s_big = c + (upper_from(B, b1, nb, v) - b1);
+      c = -1;
+    }
+    s_cnt[i] = c;
+  }
+  __syncthreads();
+  // every A key of the window: its column, and its run head's count
+  for (int i = tid; i < wa; i += NT) {
+    const K v = keys[i];
+    int h = i;
+    if (i > 0 && key_equal(keys[i - 1], v)) {
+      int l = 0, r = i;  // first key of the window equal to v
+      while (l < r) {
+        const int m = (l + r) >> 1;
+        if (keys[m] < v) l = m + 1; else r = m;
+      }
+      h = l;
+    }
+    const int c = s_cnt[h];
+    const int rl = s_lo[i] < 0 ? 0 : (s_lo[i] > wb ? wb : s_lo[i]);
+    lo_out[a0 + i] = b0 + rl;
+    cnt_out[a0 + i] = c >= 0 ? (int64_t)c : s_big;
   }
 }
 
 // Every A key starts with no run: keys that no tile visits (only possible
 // when unsorted inputs make the tiles' splits non-monotone) then count 0.
-__global__ void join_clear_kernel(int64_t *__restrict__ lo, int64_t *__restrict__ cnt, int64_t n) {
+__global__ void join_clear_kernel(int64_t *__restrict__ cnt, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    lo[i] = 0;
-    cnt[i] = 0;
-  }
+  if (i < n) cnt[i] = 0;
 }
 
 // Phase 2a: sum of each block of kScanBlock counts.
@@ -214,7 +248,7 @@ __global__ __launch_bounds__(kEmitNT) void join_emit_kernel(const int64_t *__res
                                                             const int64_t *__restrict__ lo_col,
                                                             int64_t na, int64_t *__restrict__ I,
                                                             int64_t *__restrict__ J, int64_t cap) {
-  constexpr int NT = kEmitNT, VT = kEmitVT, E = kEmitE;
+  constexpr int NT = kEmitNT, E = kEmitE;
   // off and lo of keys [a0 - 1, a1) (slot 0 is the key before the tile)
   __shared__ int64_t s_off[E + 2], s_lo[E + 2];
   __shared__ int64_t s_split[2];
@@ -245,33 +279,25 @@ __global__ __launch_bounds__(kEmitNT) void join_emit_kernel(const int64_t *__res
     const int64_t a0 = s_split[0], a1 = s_split[1];
     const int64_t p0 = d0 - a0;  // first output of the tile
     const int wa = (int)(a1 - a0);
-    const int n = (int)(d1 - d0);
+    const int n_out = (int)(d1 - d0) - wa;  // outputs p0 .. p0 + n_out - 1
     for (int i = tid; i <= wa; i += NT) {
       const int64_t k = a0 - 1 + i;
       s_off[i] = k >= 0 ? off[k] : 0;
       s_lo[i] = k >= 0 ? lo_col[k] : 0;
     }
     __syncthreads();
-    // lane split at local diagonal tid * VT: keys (s_off[1..]) against the
-    // outputs p0, p0 + 1, ...
-    const int dl = tid * VT < n ? tid * VT : n;
-    int lo, hi;
-    diag_range<int>(dl, wa, n - wa, lo, hi);
-    const int a = split_search<int>(
-        dl, lo, hi, [&](int i) { return s_off[1 + i]; }, [&](int j) { return p0 + j; });
-    int ai = a;                      // keys taken so far in the tile
-    int64_t p = p0 + (dl - a);       // next output
-    const int steps = n - dl < VT ? n - dl : VT;
-    for (int s = 0; s < steps; ++s) {
-      if (ai < wa && s_off[1 + ai] <= p) {
-        ++ai;  // key a0 + ai - 1 begins here
-      } else {
-        // output p: rows of key a0 + ai - 1
-        if (p < cap) {
-          I[p] = a0 + ai - 1;
-          J[p] = s_lo[ai] + (p - s_off[ai]);
-        }
-        ++p;
+    // output p belongs to the last key with off <= p: slot 0 (key a0 - 1)
+    // has off <= p0, slots 1 .. wa are the tile's keys
+    for (int q = tid; q < n_out; q += NT) {
+      const int64_t p = p0 + q;
+      int l = 0, r = wa;  // last slot in [0, wa] with s_off <= p
+      while (l < r) {
+        const int m = (l + r + 1) >> 1;
+        if (s_off[m] <= p) l = m; else r = m - 1;
+      }
+      if (p < cap) {
+        I[p] = a0 - 1 + l;
+        J[p] = s_lo[l] + (p - s_off[l]);
       }
     }
     __syncthreads();  // the LDS windows are reused by the next tile
@@ -296,8 +322,8 @@ hipError_t launch_join(const K *A, int64_t na, const K *B, int64_t nb, int64_t *
   int64_t *lo = ws, *off = lo + na, *bsum = off + (na + 1), *splits = bsum + n_blocks;
   hipError_t e = hipSuccess;
   if (na > 0)
-    hipLaunchKernelGGL(join_clear_kernel, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, lo,
-                       off, na);
+    hipLaunchKernelGGL(join_clear_kernel, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, off,
+                       na);
   if (n_tiles > 0) {
     e = launch_partition<K>(A, na, B, nb, nullptr, kJoinT, n_tiles + 1, splits, s);
     if (e != hipSuccess) return e;
