@@ -37,6 +37,7 @@ namespace {
 
 constexpr int kJoinNT = 256, kJoinVT = 8, kJoinT = kJoinNT * kJoinVT;   // rank tiles
 constexpr int kEmitNT = 256, kEmitE = 2048;                               // emission tiles
+constexpr int kEmitG = 8, kEmitCB = 31;  // emission splits: lanes per boundary, tiles per chunk
 constexpr int kScanPer = 4;                                              // keys per scan lane
 constexpr int64_t kScanBlock = 1024 * kScanPer;
 
@@ -242,16 +243,20 @@ __global__ __launch_bounds__(1024) void join_scan_apply_kernel(int64_t *__restri
 }
 
 // Phase 3: the pairs.  off[0..na) offsets, off[na] the total (ws), lo[]
-// the first B column of every A key.  Resident workgroups walk the tiles of
-// the combined grid (na keys + total pairs) in strides.
+// the first B column of every A key.  Each resident workgroup takes a
+// contiguous range of the tiles of the combined grid (na keys + total
+// pairs).  It finds the splits on its tiles' boundaries up front, kEmitCB + 1
+// at a time with kEmitG lanes each, so the searches' dependent loads overlap
+// one another instead of starting every tile.
 __global__ __launch_bounds__(kEmitNT) void join_emit_kernel(const int64_t *__restrict__ off,
                                                             const int64_t *__restrict__ lo_col,
                                                             int64_t na, int64_t *__restrict__ I,
                                                             int64_t *__restrict__ J, int64_t cap) {
-  constexpr int NT = kEmitNT, E = kEmitE;
+  constexpr int NT = kEmitNT, E = kEmitE, G = kEmitG, CB = kEmitCB;
+  static_assert((CB + 1) * G <= NT, "one group of lanes per boundary of a chunk");
   // off and lo of keys [a0 - 1, a1) (slot 0 is the key before the tile)
   __shared__ int64_t s_off[E + 2], s_lo[E + 2];
-  __shared__ int64_t s_split[2];
+  __shared__ int64_t s_bnd[CB + 1];  // splits on the chunk's boundaries
   const int tid = threadIdx.x;
   const int64_t total = off[na];
   const int64_t N = na + total;  // items of the combined grid
@@ -260,47 +265,72 @@ __global__ __launch_bounds__(kEmitNT) void join_emit_kernel(const int64_t *__res
   // (the work stays bounded by the caller's room, whatever the count).
   const int64_t n_all = (N + E - 1) / E, n_room = (cap + na + E - 1) / E;
   const int64_t n_tiles = n_all < n_room ? n_all : n_room;
-  // the split on diagonal d: off entries among the first d items (ties take
-  // off first: output p comes after every key with off <= p)
-  auto split_at = [&](int64_t d) -> int64_t {
-    int64_t l, h;
-    diag_range<int64_t>(d, na, total, l, h);
-    return group_split_search<64, int64_t>(
-        d, l, h, [&](int64_t i) { return off[i]; }, [&](int64_t j) { return j; });
-  };
-  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const int64_t d0 = t * E;
-    const int64_t d1 = d0 + E < N ? d0 + E : N;
-    if (tid < 128) {
-      const int64_t a = split_at(tid < 64 ? d0 : d1);
-      if ((tid & 63) == 0) s_split[tid >> 6] = a;
+  const int64_t t_begin = n_tiles * blockIdx.x / gridDim.x;
+  const int64_t t_end = n_tiles * (blockIdx.x + 1) / gridDim.x;
+  for (int64_t c0 = t_begin; c0 < t_end; c0 += CB) {
+    const int64_t c1 = c0 + CB < t_end ? c0 + CB : t_end;
+    // the split on diagonal d: off entries among the first d items (ties
+    // take off first: output p comes after every key with off <= p); a
+    // group of G lanes per boundary c0 .. c1
+    const int g = tid / G;
+    if (g <= c1 - c0) {
+      const int64_t d = (c0 + g) * E < N ? (c0 + g) * E : N;
+      int64_t l, h;
+      diag_range<int64_t>(d, na, total, l, h);
+      const int64_t a = group_split_search<G, int64_t>(
+          d, l, h, [&](int64_t i) { return off[i]; }, [&](int64_t j) { return j; });
+      if (tid % G == 0) s_bnd[g] = a;
     }
     __syncthreads();
-    const int64_t a0 = s_split[0], a1 = s_split[1];
-    const int64_t p0 = d0 - a0;  // first output of the tile
-    const int wa = (int)(a1 - a0);
-    const int n_out = (int)(d1 - d0) - wa;  // outputs p0 .. p0 + n_out - 1
-    for (int i = tid; i <= wa; i += NT) {
-      const int64_t k = a0 - 1 + i;
-      s_off[i] = k >= 0 ? off[k] : 0;
-      s_lo[i] = k >= 0 ? lo_col[k] : 0;
-    }
-    __syncthreads();
-    // output p belongs to the last key with off <= p: slot 0 (key a0 - 1)
-    // has off <= p0, slots 1 .. wa are the tile's keys
-    for (int q = tid; q < n_out; q += NT) {
-      const int64_t p = p0 + q;
-      int l = 0, r = wa;  // last slot in [0, wa] with s_off <= p
-      while (l < r) {
-        const int m = (l + r + 1) >> 1;
-        if (s_off[m] <= p) l = m; else r = m - 1;
+    // off and lo of tile t's keys, loaded into registers one tile ahead so
+    // that the loads overlap the previous tile's stores
+    constexpr int PR = (E + 1 + NT - 1) / NT;
+    int64_t r_off[PR], r_lo[PR];
+    auto fetch = [&](int64_t t) {
+      const int64_t a0 = s_bnd[t - c0];
+      const int wa = (int)(s_bnd[t - c0 + 1] - a0);
+#pragma unroll
+      for (int k = 0; k < PR; ++k) {
+        const int i = tid + k * NT;
+        const int64_t key = a0 - 1 + i;
+        r_off[k] = i <= wa && key >= 0 ? off[key] : 0;
+        r_lo[k] = i <= wa && key >= 0 ? lo_col[key] : 0;
       }
-      if (p < cap) {
-        I[p] = a0 - 1 + l;
-        J[p] = s_lo[l] + (p - s_off[l]);
+    };
+    fetch(c0);
+    for (int64_t t = c0; t < c1; ++t) {
+      const int64_t d0 = t * E;
+      const int64_t d1 = d0 + E < N ? d0 + E : N;
+      const int64_t a0 = s_bnd[t - c0], a1 = s_bnd[t - c0 + 1];
+      const int64_t p0 = d0 - a0;  // first output of the tile
+      const int wa = (int)(a1 - a0);
+      const int n_out = (int)(d1 - d0) - wa;  // outputs p0 .. p0 + n_out - 1
+#pragma unroll
+      for (int k = 0; k < PR; ++k) {
+        const int i = tid + k * NT;
+        if (i <= wa) {
+          s_off[i] = r_off[k];
+          s_lo[i] = r_lo[k];
+        }
       }
+      __syncthreads();
+      if (t + 1 < c1) fetch(t + 1);
+      // output p belongs to the last key with off <= p: slot 0 (key a0 - 1)
+      // has off <= p0, slots 1 .. wa are the tile's keys
+      for (int q = tid; q < n_out; q += NT) {
+        const int64_t p = p0 + q;
+        int l = 0, r = wa;  // last slot in [0, wa] with s_off <= p
+        while (l < r) {
+          const int m = (l + r + 1) >> 1;
+          if (s_off[m] <= p) l = m; else r = m - 1;
+        }
+        if (p < cap) {
+          I[p] = a0 - 1 + l;
+          J[p] = s_lo[l] + (p - s_off[l]);
+        }
+      }
+      __syncthreads();  // the LDS windows are reused by the next tile
     }
-    __syncthreads();  // the LDS windows are reused by the next tile
   }
 }
 
@@ -340,8 +370,9 @@ hipError_t launch_join(const K *A, int64_t na, const K *B, int64_t nb, int64_t *
     hipLaunchKernelGGL(join_scan_apply_kernel, dim3((unsigned)n_blocks), dim3(1024), 0, s, off, na,
                        bsum);
   if (na > 0 && cap > 0) {
-    // resident workgroups walk the emission tiles
-    const int grid = 8 * device_cu_count();
+    // resident workgroups (four per CU: 33 KB of LDS each) walk contiguous
+    // ranges of the emission tiles
+    const int grid = 4 * device_cu_count();
     hipLaunchKernelGGL(join_emit_kernel, dim3((unsigned)grid), dim3(kEmitNT), 0, s, off, lo, na, I,
                        J, cap);
   }
