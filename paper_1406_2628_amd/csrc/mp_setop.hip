@@ -198,44 +198,58 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     }
   }
 
+  // The walk.  rA / rB: the rank of the next A / B copy in its run, 32-bit
+  // (the lane's first ranks saturate at 2^30, past any window); fA / fB:
+  // still in the run the lane started in, whose exact 64-bit rank adds
+  // xA / xB.  A partner inside the window needs only the 32-bit rank; one
+  // outside takes the exact index and a global read.  The loser of each
+  // compare stays in a register (ka / kb).
+  const int kA0s = (int)(kA < (1 << 30) ? kA : (1 << 30));
+  const int kB0s = (int)(kB < (1 << 30) ? kB : (1 << 30));
+  const int64_t xA = kA - kA0s, xB = kB - kB0s;
+  int rA = kA0s, rB = kB0s, fA = 1, fB = 1;
+  K ka = keys[ai], kb = keys[bi];
   K out[VT];
   uint32_t keep = 0;
+  // all VT steps run: a lane whose run is shorter keeps stepping past it
+  // (reads stay below n + VT + 1 in LDS, global reads inside the arrays) and
+  // keeps none of those outputs
 #pragma unroll
   for (int s = 0; s < VT; ++s) {
-    if (s < steps) {
-      // one path for both sides (no divergence between A and B steps)
-      const bool take_b = (bi < n) && (ai >= wa || keys[bi] < keys[ai]);
-      const K v = take_b ? keys[bi] : keys[ai];
-      // rank of this copy within its run on its own side
-      if (take_b) {
-        kB = key_eq(v, lastB) ? kB : 0;
-        lastB = v;
-      } else {
-        kA = key_eq(v, lastA) ? kA : 0;
-        lastA = v;
-      }
-      const int64_t k = take_b ? kB : kA;
-      // partner: an A copy's is B[b + k] (b = the path's b, where the run
-      // starts in B); a B copy's is A[a - 1 - k] (a = the path's a, where
-      // the run ends in A)
-      const int64_t q = take_b ? a0 + ai - 1 - k : b0 + (bi - wa) + k;
-      const bool in_range = take_b ? q >= 0 : q < nb;
-      const bool in_win = take_b ? q >= a0 : q - b0 < wb;
-      bool m = false;
-      if (in_range) {
-        const K w = in_win ? keys[take_b ? (int)(q - a0) : wa + (int)(q - b0)]
-                           : (take_b ? A[q] : B[q]);
-        m = key_eq(w, v);
-      }
-      out[s] = v;
-      const bool keep_a = OP == 1 || (OP == 0 ? m : !m);
-      const bool keep_b = (OP == 1 || OP == 3) && !m;
-      if (take_b ? keep_b : keep_a) keep |= 1u << s;
-      kA += take_b ? 0 : 1;
-      kB += take_b ? 1 : 0;
-      ai += take_b ? 0 : 1;
-      bi += take_b ? 1 : 0;
+    const bool tb = (bi < n) && (ai >= wa || kb < ka);
+    const K v = tb ? kb : ka;
+    const bool same = key_eq(v, tb ? lastB : lastA);
+    // a copy that starts a new run on its side has rank 0
+    rA = !tb && !same ? 0 : rA;
+    fA = !tb && !same ? 0 : fA;
+    rB = tb && !same ? 0 : rB;
+    fB = tb && !same ? 0 : fB;
+    lastA = tb ? lastA : v;
+    lastB = tb ? v : lastB;
+    // partner: an A copy's is B[b + rank] (b = the path's b, where the run
+    // starts in B); a B copy's is A[a - 1 - rank] (a = the path's a, where
+    // the run ends in A)
+    const int r = tb ? rB : rA;
+    const int rel = tb ? ai - 1 - r : (bi - wa) + r;
+    const bool in_win = tb ? rel >= 0 : rel < wb;
+    bool m = key_eq(keys[in_win ? (tb ? rel : wa + rel) : 0], v);
+    if (!in_win) {
+      const int64_t r64 = r + (tb ? (fB ? xB : 0) : (fA ? xA : 0));
+      const int64_t q = tb ? a0 + ai - 1 - r64 : b0 + (bi - wa) + r64;
+      const bool in_range = tb ? q >= 0 : q < nb;
+      m = in_range && key_eq(tb ? A[q] : B[q], v);
     }
+    out[s] = v;
+    const bool kept = (tb ? (OP == 1 || OP == 3) && !m : OP == 1 || (OP == 0 ? m : !m)) && s < steps;
+    keep = kept ? keep | (1u << s) : keep;
+    rA += tb ? 0 : 1;
+    rB += tb ? 1 : 0;
+    const int taken = tb ? bi : ai;
+    ai = tb ? ai : taken + 1;
+    bi = tb ? taken + 1 : bi;
+    const K nxt = keys[taken + 1];
+    ka = tb ? ka : nxt;
+    kb = tb ? nxt : kb;
   }
 
   // prefix of the lanes' kept counts: a shuffle scan inside each wavefront,
