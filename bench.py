@@ -591,10 +591,11 @@ def leg_learned(args, ex):
     got = lp.partition(A, B, dev(ds)).cpu().numpy()
     res["oracle_spot_check_256"] = bool(np.array_equal(got, oracle.partition(Ah, Bh, ds)))
     # the full f32 merge (Algorithm 1 in two calls) on learned splits of the
-    # 2048-key tile diagonals, against the same on plain splits and against
-    # the built-in merge (its own tile splits, then its tiles)
+    # diagonals of the built-in merge's 16384-key tiles, against the same on
+    # plain splits and against the built-in merge (its own tile splits, then
+    # the same tile kernel)
     log("bench: learned: full f32 merge on learned splits")
-    T = 2048
+    T = 16384
     tdiag = torch.clamp(torch.arange((N + T - 1) // T + 1, device="cuda", dtype=torch.int64) * T,
                         max=N)
     sp_l = torch.empty_like(tdiag)
