@@ -633,8 +633,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; a merge would shard by "
-              "splitting the output at G-1 diagonals, but no multi-GPU path is built. "
+        print("bench.py: the library runs on one GPU only; a merge would shard by "
+              "splitting the output at G-1 diagonals, but no multi-GPU path exists. "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
