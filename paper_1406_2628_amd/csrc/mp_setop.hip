@@ -34,6 +34,7 @@
 
 #include "mp_device.h"
 #include "mp_internal.h"
+#include "mp_lookback.h"
 
 namespace mp {
 
@@ -74,13 +75,6 @@ __device__ int64_t wave_first_true(int64_t lo, int64_t hi, P pred) {
   }
   return lo;
 }
-
-// Tile status words of the look-back: 0 = nothing published yet, else a
-// flag in the top two bits and a count below.
-constexpr unsigned long long kSetAggregate = 1ull << 62;  // this tile's own count
-constexpr unsigned long long kSetInclusive = 2ull << 62;  // count of all tiles up to it
-constexpr unsigned long long kSetValue = (1ull << 62) - 1;
-constexpr unsigned kSetMaxPolls = 1u << 22;  // far beyond any real wait
 
 // Start of the run of keys equal to X[p] (p > 0), by the 64 lanes of the
 // calling wavefront: one round over the 64 keys before p, then, for a
@@ -271,43 +265,11 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     incl += w < wave ? t : 0;
     total += t;
   }
-  // output offset: publish this tile's count, then add up the tiles before
-  // it, wave 0 reading 64 of them per round (nearest first) back to the
-  // nearest one that has published its inclusive count
+  // output offset: publish this tile's count and look back over the tiles
+  // before it (wave 0)
   if (tid < 64) {
-    int64_t excl = 0;
-    bool gave_up = false;
-    if (tile == 0) {
-      if (tid == 0) atomicExch(&status[0], kSetInclusive | (unsigned long long)total);
-    } else {
-      if (tid == 0) atomicExch(&status[tile], kSetAggregate | (unsigned long long)total);
-      int64_t j_hi = tile - 1;
-      unsigned polls = 0;
-      while (true) {
-        const int64_t j = j_hi - tid;
-        // before tile 0: an inclusive count of 0
-        const unsigned long long v = j >= 0 ? atomicAdd(&status[j], 0ull) : kSetInclusive;
-        const uint64_t inc = __ballot((v & kSetInclusive) != 0);
-        const uint64_t empty = __ballot(v == 0);
-        const int f = inc ? __ffsll((long long)inc) - 1 : 64;  // nearest inclusive lane
-        const uint64_t upto = f >= 63 ? ~0ull : ((2ull << f) - 1);  // lanes 0..f
-        if (empty & upto) {
-          // a tile in range has not published yet: read the window again
-          if (++polls > kSetMaxPolls) {
-            gave_up = true;  // an offset too small keeps the writes in bounds
-            break;
-          }
-          continue;
-        }
-        unsigned long long x = tid <= f ? (v & kSetValue) : 0ull;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-        excl += (int64_t)x;
-        if (f < 64) break;
-        j_hi -= 64;
-      }
-      if (tid == 0) atomicExch(&status[tile], kSetInclusive | (unsigned long long)(excl + total));
-    }
+    bool gave_up;
+    const int64_t excl = lookback_exclusive(status, tile, total, &gave_up);
     if (tid == 0) {
       s_excl = excl;
       const int64_t end = excl + total < cap ? excl + total : cap;
