@@ -38,12 +38,34 @@
 
 namespace mp {
 
-// 512 lanes per tile, each taking 24 outputs for 4-byte keys and 12 for
-// 8-byte keys (48 KiB of LDS either way)
+// 512 lanes per tile, each taking 25 outputs for 4-byte keys and 13 for
+// 8-byte keys (about 50 KiB of LDS either way, three workgroups per CU).  An
+// odd count keeps the lanes' LDS cursors, half a lane's outputs apart in
+// each window, off a shared bank.
 constexpr int kSetNT = 512;
 template <typename K>
-constexpr int kSetVT = sizeof(K) == 4 ? 24 : 12;
-constexpr int kSetTMin = kSetNT * 12;  // the smaller tile, for workspace bounds
+constexpr int kSetVT = sizeof(K) == 4 ? 25 : 13;
+constexpr int kSetTMin = kSetNT * 12;  // at most the smaller tile: bounds the tile count
+// keys per 16-byte chunk of the window loads and output stores
+template <typename K>
+constexpr int kSetCH = 16 / (int)sizeof(K);
+
+// The chunk X[g, g + CH) of an array of lim keys.  Chunks sit on a grid
+// aligned to 16 bytes in memory, so one that lies inside the array is one
+// nontemporal vector load; at the array's ends (g may be negative) only the
+// keys inside it are read.
+template <typename K>
+__device__ __forceinline__ void set_load_chunk(const K *__restrict__ X, int64_t g, int64_t lim,
+                                               K (&v)[kSetCH<K>]) {
+  constexpr int CH = kSetCH<K>;
+  if (g >= 0 && g + CH <= lim) {
+    *reinterpret_cast<u32x4 *>(v) =
+        __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(X + g));
+  } else {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) v[j] = g + j >= 0 && g + j < lim ? X[g + j] : K{};
+  }
+}
 
 template <typename K>
 __device__ __forceinline__ bool key_eq(K x, K y) {
@@ -104,7 +126,10 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     unsigned long long *__restrict__ ticket, int64_t n_tiles, int64_t *__restrict__ count,
     K *__restrict__ S, int64_t cap) {
   constexpr int NT = kSetNT, VT = kSetVT<K>, T = NT * VT;
-  __shared__ K keys[T + VT + 1];
+  constexpr int CH = kSetCH<K>;
+  // both windows' chunks (at most T + 4 CH - 4 keys) and the slack the walk
+  // reads past the end of B's window
+  __shared__ __align__(16) K keys[T + 4 * CH + VT + 1];
   __shared__ int s_cnt[NT / 64];
   __shared__ int64_t s_lb[2], s_tile, s_excl;
   const int tid = threadIdx.x;
@@ -126,14 +151,26 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
   const int64_t wa_hi = na - a0 < (int64_t)n ? na - a0 : (int64_t)n;
   wa64 = wa64 < wa_lo ? wa_lo : (wa64 > wa_hi ? wa_hi : wa64);
   const int wa = (int)wa64, wb = n - wa;
-  // the pair back to back in LDS: each lane issues all its VT loads into
-  // registers before the first LDS write, so they are in flight together
-  K stage[VT];
+  // the pair back to back in LDS (A's window at 0, B's at wa), read in
+  // 16-byte chunks on a grid aligned in memory, stored whole into LDS: A's
+  // from position 0 and B's after them, so A[a0] sits at oa and B[b0] at
+  // ob, and each window ends at ae / be.  Each lane issues all its chunk
+  // loads into registers before the first LDS write, so they are in flight
+  // together.
+  constexpr int PV = (T / CH + 4 + NT - 1) / NT;  // ca + cb <= T / CH + 3
+  const int sa = (int)(((uintptr_t)(A + a0) / sizeof(K)) & (CH - 1));
+  const int sb = (int)(((uintptr_t)(B + b0) / sizeof(K)) & (CH - 1));
+  const int ca = (sa + wa + CH - 1) / CH, cb = (sb + wb + CH - 1) / CH;
+  const int oa = sa, ob = ca * CH + sb, ae = oa + wa, be = ob + wb;
+  K stage[PV][CH];
 #pragma unroll
-  for (int s = 0; s < VT; ++s) {
-    const int i = tid + s * NT;
-    const K *p = i < wa ? A + (a0 + i) : B + (b0 + (i - wa));
-    if (i < n) stage[s] = *p;
+  for (int k = 0; k < PV; ++k) {
+    const int c = tid + k * NT;
+    if (c < ca + cb) {
+      const bool fb = c >= ca;
+      const int64_t g = fb ? b0 - sb + (int64_t)(c - ca) * CH : a0 - sa + (int64_t)c * CH;
+      set_load_chunk<K>(fb ? B : A, g, fb ? nb : na, stage[k]);
+    }
   }
   // run starts of the window's first A and first B value (global search only
   // when the run reaches back past the window)
@@ -147,9 +184,9 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
     }
   }
 #pragma unroll
-  for (int s = 0; s < VT; ++s) {
-    const int i = tid + s * NT;
-    if (i < n) keys[i] = stage[s];
+  for (int k = 0; k < PV; ++k) {
+    const int c = tid + k * NT;
+    if (c < ca + cb) *reinterpret_cast<u32x4 *>(keys + c * CH) = *reinterpret_cast<u32x4 *>(stage[k]);
   }
   __syncthreads();
 
@@ -158,93 +195,98 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
   int lo, hi;
   diag_range<int>(dl, wa, wb, lo, hi);
   const int a = split_search<int>(
-      dl, lo, hi, [&](int i) { return keys[i]; }, [&](int j) { return keys[wa + j]; });
-  int ai = a, bi = wa + dl - a;  // LDS positions
+      dl, lo, hi, [&](int i) { return keys[oa + i]; }, [&](int j) { return keys[ob + j]; });
+  int ai = oa + a, bi = ob + dl - a;  // LDS positions
   const int steps = n - dl < VT ? n - dl : VT;
   // ranks of the first A and B copies this lane takes
   int64_t kA = 0, kB = 0;
-  K lastA{}, lastB{};
   // (a search only when the key before it in the window is equal)
-  if (ai < wa) {
-    lastA = keys[ai];
-    if (ai > 0 && key_eq(keys[ai - 1], lastA)) {
-      int l = 0, h = ai - 1;  // first position in [0, ai - 1] holding lastA
+  if (ai < ae) {
+    const K v = keys[ai];
+    if (ai > oa && key_eq(keys[ai - 1], v)) {
+      int l = oa, h = ai - 1;  // first position in [oa, ai - 1] holding v
       while (l < h) {
         const int m = (l + h) >> 1;
-        if (keys[m] < lastA) l = m + 1; else h = m;
+        if (keys[m] < v) l = m + 1; else h = m;
       }
-      kA = (a0 + ai) - (l > 0 ? a0 + l : s_lb[0]);
+      kA = l > oa ? ai - l : (a0 + (ai - oa)) - s_lb[0];
     } else {
-      kA = ai > 0 ? 0 : (a0 + ai) - s_lb[0];
+      kA = ai > oa ? 0 : a0 - s_lb[0];
     }
   }
-  if (bi < n) {
-    lastB = keys[bi];
-    if (bi > wa && key_eq(keys[bi - 1], lastB)) {
-      int l = wa, h = bi - 1;
+  if (bi < be) {
+    const K v = keys[bi];
+    if (bi > ob && key_eq(keys[bi - 1], v)) {
+      int l = ob, h = bi - 1;
       while (l < h) {
         const int m = (l + h) >> 1;
-        if (keys[m] < lastB) l = m + 1; else h = m;
+        if (keys[m] < v) l = m + 1; else h = m;
       }
-      kB = (b0 + (bi - wa)) - (l > wa ? b0 + (l - wa) : s_lb[1]);
+      kB = l > ob ? bi - l : (b0 + (bi - ob)) - s_lb[1];
     } else {
-      kB = bi > wa ? 0 : (b0 + (bi - wa)) - s_lb[1];
+      kB = bi > ob ? 0 : b0 - s_lb[1];
     }
   }
 
-  // The walk.  rA / rB: the rank of the next A / B copy in its run, 32-bit
-  // (the lane's first ranks saturate at 2^30, past any window); fA / fB:
-  // still in the run the lane started in, whose exact 64-bit rank adds
-  // xA / xB.  A partner inside the window needs only the 32-bit rank; one
-  // outside takes the exact index and a global read.  The loser of each
-  // compare stays in a register (ka / kb).
+  // The walk.  sA / sB: the LDS position where the run of the next A / B
+  // copy starts, so a copy taken at position p has rank p - sA (or p - sB).
+  // The lane's first runs may start far before the window: their starts are
+  // placed at most 2^30 back, and a partner lookup through such a run adds
+  // the exact rest (xA / xB) while the start is still the first one.  A
+  // partner inside the window is one LDS read; one outside it takes the
+  // exact index and a global read.  When a copy is taken, the key after it
+  // on its side says whether the next copy continues the run.  The loser of
+  // each compare stays in a register (ka / kb).
   const int kA0s = (int)(kA < (1 << 30) ? kA : (1 << 30));
   const int kB0s = (int)(kB < (1 << 30) ? kB : (1 << 30));
   const int64_t xA = kA - kA0s, xB = kB - kB0s;
-  int rA = kA0s, rB = kB0s, fA = 1, fB = 1;
+  const int sA0 = ai - kA0s, sB0 = bi - kB0s;
+  int sA = sA0, sB = sB0;
   K ka = keys[ai], kb = keys[bi];
   K out[VT];
   uint32_t keep = 0;
   // all VT steps run: a lane whose run is shorter keeps stepping past it
-  // (reads stay below n + VT + 1 in LDS, global reads inside the arrays) and
-  // keeps none of those outputs
+  // (LDS reads stay below be + VT + 1, global reads inside the arrays);
+  // the outputs past its run are masked off after the walk
 #pragma unroll
   for (int s = 0; s < VT; ++s) {
-    const bool tb = (bi < n) && (ai >= wa || kb < ka);
+    const bool tb = (bi < be) && (ai >= ae || kb < ka);
     const K v = tb ? kb : ka;
-    const bool same = key_eq(v, tb ? lastB : lastA);
-    // a copy that starts a new run on its side has rank 0
-    rA = !tb && !same ? 0 : rA;
-    fA = !tb && !same ? 0 : fA;
-    rB = tb && !same ? 0 : rB;
-    fB = tb && !same ? 0 : fB;
-    lastA = tb ? lastA : v;
-    lastB = tb ? v : lastB;
+    const int pos = tb ? bi : ai;
+    const int st = tb ? sB : sA;
+    const int r = pos - st;
     // partner: an A copy's is B[b + rank] (b = the path's b, where the run
     // starts in B); a B copy's is A[a - 1 - rank] (a = the path's a, where
-    // the run ends in A)
-    const int r = tb ? rB : rA;
-    const int rel = tb ? ai - 1 - r : (bi - wa) + r;
-    const bool in_win = tb ? rel >= 0 : rel < wb;
-    bool m = key_eq(keys[in_win ? (tb ? rel : wa + rel) : 0], v);
+    // the run ends in A).  As LDS positions: bi + r, inside B's window when
+    // below be, and ai - 1 - r, inside A's when at least oa; one unsigned
+    // compare against [oa, be) tells both.
+    const int idx = tb ? ai - 1 - r : bi + r;
+    const bool in_win = (unsigned)(idx - oa) < (unsigned)(be - oa);
+    bool m = key_eq(keys[in_win ? idx : 0], v);
     if (!in_win) {
-      const int64_t r64 = r + (tb ? (fB ? xB : 0) : (fA ? xA : 0));
-      const int64_t q = tb ? a0 + ai - 1 - r64 : b0 + (bi - wa) + r64;
+      const int64_t r64 = r + (tb ? (st == sB0 ? xB : 0) : (st == sA0 ? xA : 0));
+      const int64_t q = tb ? a0 + (ai - oa) - 1 - r64 : b0 + (bi - ob) + r64;
       const bool in_range = tb ? q >= 0 : q < nb;
       m = in_range && key_eq(tb ? A[q] : B[q], v);
     }
     out[s] = v;
-    const bool kept = (tb ? (OP == 1 || OP == 3) && !m : OP == 1 || (OP == 0 ? m : !m)) && s < steps;
+    const bool kept = tb ? (OP == 1 || OP == 3) && !m : OP == 1 || (OP == 0 ? m : !m);
     keep = kept ? keep | (1u << s) : keep;
-    rA += tb ? 0 : 1;
-    rB += tb ? 1 : 0;
-    const int taken = tb ? bi : ai;
-    ai = tb ? ai : taken + 1;
-    bi = tb ? taken + 1 : bi;
-    const K nxt = keys[taken + 1];
+    // an empty asm that reads and writes keep in a VGPR: it pins the update
+    // to this step instead of letting every step's decision stay live in
+    // scalar registers until the end of the walk
+    asm volatile("" : "+v"(keep));
+    const int p1 = pos + 1;
+    const K nxt = keys[p1];
+    const int st1 = key_eq(nxt, v) ? st : p1;
+    ai = tb ? ai : p1;
+    bi = tb ? p1 : bi;
     ka = tb ? ka : nxt;
     kb = tb ? nxt : kb;
+    sA = tb ? sA : st1;
+    sB = tb ? st1 : sB;
   }
+  keep &= steps >= 32 ? ~0u : (1u << steps) - 1u;
 
   // prefix of the lanes' kept counts: a shuffle scan inside each wavefront,
   // then the wavefront totals through LDS
@@ -278,16 +320,34 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
         atomicCAS((unsigned long long *)count, 0ull, (unsigned long long)end);
     }
   }
-  // compact through LDS (the windows are no longer read), then store
-  int pos = incl - c;
+  // compact through LDS (the windows are no longer read) from position so,
+  // where the output's 16-byte grid in memory falls, then store whole
+  // chunks as one vector each (element stores for the parts of the end
+  // chunks that belong to this tile)
+  __syncthreads();
+  const int64_t base = s_excl;
+  const int so = (int)(((uintptr_t)(S + base) / sizeof(K)) & (CH - 1));
+  int pos = so + incl - c;
 #pragma unroll
   for (int s = 0; s < VT; ++s)
     if ((keep >> s) & 1u) keys[pos++] = out[s];
   __syncthreads();
-  const int64_t base = s_excl;
   const int64_t room = cap - base;  // slots of S left from this tile's offset
   const int lim = room < (int64_t)total ? (room > 0 ? (int)room : 0) : total;
-  for (int i = tid; i < lim; i += NT) S[base + i] = keys[i];
+  if (lim > 0) {
+    const int nc = (so + lim + CH - 1) / CH;
+    for (int ci = tid; ci < nc; ci += NT) {
+      const int w0 = ci * CH - so;  // tile position of the chunk's first key
+      if (w0 >= 0 && w0 + CH <= lim) {
+        __builtin_nontemporal_store(*reinterpret_cast<const u32x4 *>(keys + ci * CH),
+                                    reinterpret_cast<u32x4 *>(S + (base + w0)));
+      } else {
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+          if (w0 + j >= 0 && w0 + j < lim) S[base + w0 + j] = keys[ci * CH + j];
+      }
+    }
+  }
 }
 
 // Zero the look-back state: tile status words, the ticket counter and the

@@ -92,3 +92,28 @@ def test_set_op_lookback_over_many_tiles(mp, orc, op, dt):
     A = np.sort(g.integers(0, 2_000_000, 1_500_007)).astype(npd)
     B = np.sort(g.integers(0, 2_000_000, 1_300_001)).astype(npd)
     _check(mp, orc, op, A, B)
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dt", [gen.U32, gen.U64])
+def test_set_op_unaligned_views(mp, orc, op, dt):
+    """A, B and S as views at element offsets that leave them off the 16-byte
+    grid: the windows are read and the output written in chunks aligned in
+    memory, with element accesses at the ends."""
+    from gpu_util import dev, host
+    g = np.random.default_rng(89)
+    npd = gen.NP_DTYPE[dt]
+    A = np.sort(g.integers(0, 40_000, 70_001)).astype(npd)
+    B = np.sort(g.integers(0, 40_000, 50_003)).astype(npd)
+    want = orc.set_op(op, A, B)
+    for oa, ob, os_ in ((1, 2, 3), (3, 0, 1), (2, 1, 0), (0, 3, 2)):
+        dA = dev(np.concatenate([np.zeros(oa, npd), A]))[oa:]
+        dB = dev(np.concatenate([np.zeros(ob, npd), B]))[ob:]
+        cap = len(A) + len(B)
+        base = dev(np.full(cap + os_ + 8, 0x5A, npd))
+        out, count = mp.set_op(op, dA, dB, out=base[os_:os_ + cap], sync=False)
+        k = int(host(count)[0])
+        full = host(base)
+        assert k == len(want), (op, oa, ob, os_, k, len(want))
+        assert full[os_:os_ + k].tobytes() == want.tobytes(), (op, oa, ob, os_)
+        assert np.all(full[:os_] == 0x5A) and np.all(full[os_ + cap:] == 0x5A), (op, oa, ob, os_)
