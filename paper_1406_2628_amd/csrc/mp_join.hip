@@ -14,7 +14,8 @@
 //    continues in global memory.  Each A key gets lo[i] = b and c[i] = c,
 //    written by consecutive lanes for consecutive keys.
 // 2. Offsets: an exclusive scan of c over A gives each A key the position of
-//    its first pair, and the total, which goes to *count.
+//    its first pair, and the total, which goes to *count.  The rank tiles
+//    already add their counts into the scan's block sums.
 // 3. Pairs (join_emit_kernel), balanced whatever the duplicates: output p
 //    belongs to the last A key i with off[i] <= p.  That is again a merge:
 //    of off[] (non-decreasing) with the output indices 0, 1, 2, ..., ties
@@ -46,6 +47,23 @@ __device__ __forceinline__ bool key_equal(K x, K y) {
   return !(x < y) && !(y < x);
 }
 
+// The chunk X[g, g + CH) of an array of lim keys.  Chunks sit on a grid
+// aligned to 16 bytes in memory, so one that lies inside the array is one
+// nontemporal vector load; at the array's ends (g may be negative) only the
+// keys inside it are read.
+template <typename K>
+__device__ __forceinline__ void join_load_chunk(const K *__restrict__ X, int64_t g, int64_t lim,
+                                                K (&v)[16 / sizeof(K)]) {
+  constexpr int CH = 16 / (int)sizeof(K);
+  if (g >= 0 && g + CH <= lim) {
+    *reinterpret_cast<u32x4 *>(v) =
+        __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(X + g));
+  } else {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) v[j] = g + j >= 0 && g + j < lim ? X[g + j] : K{};
+  }
+}
+
 // First index in [lo, hi) of B whose key is above v (hi if none); B is
 // sorted.  Galloping from lo, then a binary search, so a short run costs
 // few probes.
@@ -68,13 +86,17 @@ __device__ int64_t upper_from(const K *__restrict__ B, int64_t lo, int64_t hi, K
 template <typename K>
 __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
     const K *__restrict__ A, int64_t na, const K *__restrict__ B, int64_t nb,
-    const int64_t *__restrict__ a_split, int64_t *__restrict__ lo_out,
-    int64_t *__restrict__ cnt_out) {
+    const int64_t *__restrict__ a_split, int64_t n_tiles, int64_t *__restrict__ lo_out,
+    int64_t *__restrict__ cnt_out, int64_t *__restrict__ bsum) {
   constexpr int NT = kJoinNT, VT = kJoinVT, T = kJoinT;
-  __shared__ K keys[T + VT + 1];
+  constexpr int CH = 16 / (int)sizeof(K);
+  // both windows' chunks (at most T + 4 CH - 4 keys) and the slack the walk
+  // reads past the end of B's window
+  __shared__ __align__(16) K keys[T + 4 * CH + VT + 1];
   __shared__ int32_t s_lo[T];   // per A key of the window: first B column, from b0
   __shared__ int32_t s_cnt[T];  // per run head: B run length in the window, -1 past it
   __shared__ int64_t s_big;     // the B run length of the value that goes past it
+  __shared__ int64_t s_part[2][NT / 64];
   const int tid = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t N = na + nb;
@@ -92,17 +114,29 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
   wa64 = wa64 < wa_lo ? wa_lo : (wa64 > wa_hi ? wa_hi : wa64);
   const int wa = (int)wa64, wb = n - wa;
   const int64_t b1 = b0 + wb;  // first B key after the window
+  // 16-byte chunks on a grid aligned in memory, stored whole into LDS: A's
+  // from position 0 and B's after them, so A[a0] sits at oa and B[b0] at
+  // ob, and the windows end at ae and be
+  const int sa = (int)(((uintptr_t)(A + a0) / sizeof(K)) & (CH - 1));
+  const int sb = (int)(((uintptr_t)(B + b0) / sizeof(K)) & (CH - 1));
+  const int ca = (sa + wa + CH - 1) / CH, cb = (sb + wb + CH - 1) / CH;
+  const int oa = sa, ob = ca * CH + sb, ae = oa + wa, be = ob + wb;
   {
-    K r[VT];
+    constexpr int PV = (T / CH + 4 + NT - 1) / NT;  // ca + cb <= T / CH + 3
+    K r[PV][CH];
 #pragma unroll
-    for (int s = 0; s < VT; ++s) {
-      const int i = tid + s * NT;
-      if (i < n) r[s] = i < wa ? A[a0 + i] : B[b0 + (i - wa)];
+    for (int k = 0; k < PV; ++k) {
+      const int c = tid + k * NT;
+      if (c < ca + cb) {
+        const bool fb = c >= ca;
+        const int64_t g = fb ? b0 - sb + (int64_t)(c - ca) * CH : a0 - sa + (int64_t)c * CH;
+        join_load_chunk<K>(fb ? B : A, g, fb ? nb : na, r[k]);
+      }
     }
 #pragma unroll
-    for (int s = 0; s < VT; ++s) {
-      const int i = tid + s * NT;
-      if (i < n) keys[i] = r[s];
+    for (int k = 0; k < PV; ++k) {
+      const int c = tid + k * NT;
+      if (c < ca + cb) *reinterpret_cast<u32x4 *>(keys + c * CH) = *reinterpret_cast<u32x4 *>(r[k]);
     }
   }
   if (tid == 0) s_big = 0;
@@ -114,15 +148,15 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
     int lo, hi;
     diag_range<int>(dl, wa, wb, lo, hi);
     const int a = split_search<int>(
-        dl, lo, hi, [&](int i) { return keys[i]; }, [&](int j) { return keys[wa + j]; });
-    int ai = a, bi = wa + (dl - a);
+        dl, lo, hi, [&](int i) { return keys[oa + i]; }, [&](int j) { return keys[ob + j]; });
+    int ai = oa + a, bi = ob + (dl - a);
     const int steps = n - dl < VT ? n - dl : VT;
     K ka = keys[ai], kb = keys[bi];
 #pragma unroll
     for (int s = 0; s < VT; ++s) {
       if (s < steps) {
-        const bool take_b = (bi < n) && (ai >= wa || kb < ka);
-        if (!take_b && ai < wa) s_lo[ai] = bi - wa;
+        const bool take_b = (bi < be) && (ai >= ae || kb < ka);
+        if (!take_b && ai < ae) s_lo[ai - oa] = bi - ob;
         const int taken = take_b ? bi : ai;
         ai = take_b ? ai : taken + 1;
         bi = take_b ? taken + 1 : bi;
@@ -137,17 +171,17 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
   // window from the first column; only the value equal to the window's last
   // B key can go on past it
   for (int i = tid; i < wa; i += NT) {
-    const K v = keys[i];
-    if (i > 0 && key_equal(keys[i - 1], v)) continue;
-    const int j0 = wa + (s_lo[i] < 0 ? 0 : (s_lo[i] > wb ? wb : s_lo[i]));
+    const K v = keys[oa + i];
+    if (i > 0 && key_equal(keys[oa + i - 1], v)) continue;
+    const int j0 = ob + (s_lo[i] < 0 ? 0 : (s_lo[i] > wb ? wb : s_lo[i]));
     int l = j0;
-    if (j0 < n && key_equal(keys[j0], v)) {
+    if (j0 < be && key_equal(keys[j0], v)) {
       int base = j0, step = 1;
-      while (base + step < n && key_equal(keys[base + step], v)) {
+      while (base + step < be && key_equal(keys[base + step], v)) {
         base += step;
         step <<= 1;
       }
-      int lo2 = base + 1, hi2 = base + step < n ? base + step : n;
+      int lo2 = base + 1, hi2 = base + step < be ? base + step : be;
       while (lo2 < hi2) {
         const int m = (lo2 + hi2) >> 1;
         if (key_equal(keys[m], v)) lo2 = m + 1; else hi2 = m;
@@ -155,52 +189,80 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
       l = lo2;
     }
     int c = l - j0;
-    if (l == n && b1 < nb && key_equal(B[b1], v)) {
+    if (l == be && b1 < nb && key_equal(B[b1], v)) {
       s_big = c + (upper_from(B, b1, nb, v) - b1);
       c = -1;
     }
     s_cnt[i] = c;
   }
   __syncthreads();
-  // every A key of the window: its column, and its run head's count
+  // every A key of the window: its column, and its run head's count.  The
+  // counts also add up per scan block of A: a window of at most T keys
+  // touches at most two blocks (blk0 and the next).
+  const int64_t blk0 = a0 / kScanBlock;
+  int64_t part0 = 0, part1 = 0;
   for (int i = tid; i < wa; i += NT) {
-    const K v = keys[i];
+    const K v = keys[oa + i];
     int h = i;
-    if (i > 0 && key_equal(keys[i - 1], v)) {
+    if (i > 0 && key_equal(keys[oa + i - 1], v)) {
       int l = 0, r = i;  // first key of the window equal to v
       while (l < r) {
         const int m = (l + r) >> 1;
-        if (keys[m] < v) l = m + 1; else r = m;
+        if (keys[oa + m] < v) l = m + 1; else r = m;
       }
       h = l;
     }
     const int c = s_cnt[h];
     const int rl = s_lo[i] < 0 ? 0 : (s_lo[i] > wb ? wb : s_lo[i]);
     lo_out[a0 + i] = b0 + rl;
-    cnt_out[a0 + i] = c >= 0 ? (int64_t)c : s_big;
+    const int64_t cv = c >= 0 ? (int64_t)c : s_big;
+    cnt_out[a0 + i] = cv;
+    if ((a0 + i) / kScanBlock == blk0) part0 += cv; else part1 += cv;
+  }
+  // A keys between this window and the next tile's, which no tile visits
+  // (none for sorted inputs, whose splits increase), get no pairs; so every
+  // count is defined without clearing all of them first
+  if (tile + 1 < n_tiles) {
+    const int64_t lo0n = d1 > nb ? d1 - nb : 0, hi0n = d1 < na ? d1 : na;
+    int64_t a0n = a_split[tile + 1];
+    a0n = a0n < lo0n ? lo0n : (a0n > hi0n ? hi0n : a0n);
+    for (int64_t i = a0 + wa + tid; i < a0n; i += NT) cnt_out[i] = 0;
+  }
+  // the two partial block sums over the workgroup, added into the scan's
+  // block sums (zeroed before this kernel; one atomic per touched block, at
+  // addresses of their own).  Every nonzero count left in cnt_out was added
+  // by the tile that wrote it, so a block sum is never below its counts'
+  // sum and the offsets stay non-decreasing even for unsorted inputs.
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    part0 += __shfl_xor(part0, o);
+    part1 += __shfl_xor(part1, o);
+  }
+  if ((tid & 63) == 0) {
+    s_part[0][tid >> 6] = part0;
+    s_part[1][tid >> 6] = part1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int64_t p0 = 0, p1 = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      p0 += s_part[0][w];
+      p1 += s_part[1][w];
+    }
+    if (p0 != 0) atomicAdd((unsigned long long *)&bsum[blk0], (unsigned long long)p0);
+    if (p1 != 0) atomicAdd((unsigned long long *)&bsum[blk0 + 1], (unsigned long long)p1);
   }
 }
 
-// Every A key starts with no run: keys that no tile visits (only possible
-// when unsorted inputs make the tiles' splits non-monotone) then count 0.
-__global__ void join_clear_kernel(int64_t *__restrict__ cnt, int64_t n) {
+// Zeroes the scan's block sums, which the rank tiles add into.
+__global__ void join_zero_kernel(int64_t *__restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) cnt[i] = 0;
+  if (i < n) p[i] = 0;
 }
 
-// Phase 2a: sum of each block of kScanBlock counts.
-__global__ __launch_bounds__(1024) void join_scan_sums_kernel(const int64_t *__restrict__ cnt,
-                                                              int64_t n, int64_t *__restrict__ bsum) {
-  const int64_t k0 = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
-  int64_t c = 0;
-#pragma unroll
-  for (int i = 0; i < kScanPer; ++i)
-    if (k0 + i < n) c += cnt[k0 + i];
-  int64_t total;
-  workgroup_scan1024(c, &total);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
-
+// Phase 2a is in the rank kernel: each tile adds its counts into the sums
+// of the blocks of kScanBlock A keys it touches.
 // Phase 2b (one workgroup): block sums to exclusive block offsets; the
 // grand total goes to *count.
 __global__ __launch_bounds__(1024) void join_scan_blocks_kernel(int64_t *__restrict__ bsum,
@@ -351,19 +413,16 @@ hipError_t launch_join(const K *A, int64_t na, const K *B, int64_t nb, int64_t *
   const int64_t n_tiles = (na + nb + kJoinT - 1) / kJoinT;
   int64_t *lo = ws, *off = lo + na, *bsum = off + (na + 1), *splits = bsum + n_blocks;
   hipError_t e = hipSuccess;
-  if (na > 0)
-    hipLaunchKernelGGL(join_clear_kernel, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, off,
-                       na);
+  if (n_blocks > 0)
+    hipLaunchKernelGGL(join_zero_kernel, dim3((unsigned)((n_blocks + 255) / 256)), dim3(256), 0, s,
+                       bsum, n_blocks);
   if (n_tiles > 0) {
     e = launch_partition<K>(A, na, B, nb, nullptr, kJoinT, n_tiles + 1, splits, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((join_rank_kernel<K>), dim3((unsigned)n_tiles), dim3(kJoinNT), 0, s, A, na,
-                       B, nb, splits, lo, off);
+                       B, nb, splits, n_tiles, lo, off, bsum);
   }
   // (with no A keys the scan still writes the zero total)
-  if (n_blocks > 0)
-    hipLaunchKernelGGL(join_scan_sums_kernel, dim3((unsigned)n_blocks), dim3(1024), 0, s, off, na,
-                       bsum);
   hipLaunchKernelGGL(join_scan_blocks_kernel, dim3(1), dim3(1024), 0, s, bsum, n_blocks, off + na,
                      count);
   if (n_blocks > 0)
