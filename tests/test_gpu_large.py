@@ -122,6 +122,43 @@ def test_set_ops_past_2p32_outputs(mp):
             assert torch.equal(got, want), (op, s)
 
 
+@pytest.mark.parametrize("m,k", [((1 << 30) + 12345, (1 << 30) + 54321),
+                                 ((1 << 30) + 54321, (1 << 30) + 12345)])
+def test_set_ops_runs_longer_than_2p30(mp, m, k):
+    """One value repeated more than 2^30 times in each input (m copies in A,
+    k in B, between other values).  Lanes deep inside the run hold ranks
+    past 2^30, which the walk keeps exact in 64 bits; every output is a
+    closed form of m and k (the standard library's multiset counts)."""
+    import torch
+    _need(40)
+    i32 = torch.int32
+
+    def seq(*parts):
+        return torch.cat([torch.full((c,), v, dtype=i32, device="cuda") for v, c in parts if c > 0])
+
+    A = seq((7, m), (11, 100))
+    B = seq((5, 10), (7, k), (9, 50))
+    out = torch.empty(len(A) + len(B), dtype=i32, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    ws = torch.empty(mp.lib().mp_set_op_workspace_bytes(len(A), len(B)), dtype=torch.uint8,
+                     device="cuda")
+    expect = {"intersection": [(7, min(m, k))],
+              "union": [(5, 10), (7, max(m, k)), (9, 50), (11, 100)],
+              "difference": [(7, max(0, m - k)), (11, 100)],
+              "symmetric_difference": [(5, 10), (7, abs(m - k)), (9, 50), (11, 100)]}
+    for op, parts in expect.items():
+        mp.set_op(op, A, B, out=out, count=cnt, ws=ws, sync=False)
+        torch.cuda.synchronize()
+        length = sum(c for _, c in parts)
+        assert int(cnt.item()) == length, op
+        pos = 0
+        for v, c in parts:
+            assert bool((out[pos:pos + c] == v).all()), (op, v)
+            pos += c
+    del A, B, out, ws
+    torch.cuda.empty_cache()
+
+
 def test_sort_kv_past_2p31_keys(mp):
     import torch
     _need(40)
