@@ -136,7 +136,8 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
 #pragma unroll
     for (int k = 0; k < PV; ++k) {
       const int c = tid + k * NT;
-      if (c < ca + cb) *reinterpret_cast<u32x4 *>(keys + c * CH) = *reinterpret_cast<u32x4 *>(r[k]);
+      if (c < ca + cb)
+        *reinterpret_cast<u32x4 *>(keys + c * CH) = *reinterpret_cast<const u32x4 *>(r[k]);
     }
   }
   if (tid == 0) s_big = 0;

@@ -20,7 +20,8 @@
 // The rank of the first A (and B) copy a lane takes comes from a lower-bound
 // search in the tile's LDS window; only the window's first value can have its
 // run start before the window, and wave 0 finds that start in global memory
-// once per tile.  Ranks then advance along the lane's serial merge.
+// once per tile.  Along the lane's serial merge each side then keeps where
+// its current run starts, and a copy's rank is its distance from there.
 //
 // One pass: each tile's kept keys are compacted through LDS and written at
 // the tile's output offset, found by a decoupled look-back over the tiles
@@ -151,12 +152,11 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
   const int64_t wa_hi = na - a0 < (int64_t)n ? na - a0 : (int64_t)n;
   wa64 = wa64 < wa_lo ? wa_lo : (wa64 > wa_hi ? wa_hi : wa64);
   const int wa = (int)wa64, wb = n - wa;
-  // the pair back to back in LDS (A's window at 0, B's at wa), read in
-  // 16-byte chunks on a grid aligned in memory, stored whole into LDS: A's
-  // from position 0 and B's after them, so A[a0] sits at oa and B[b0] at
-  // ob, and each window ends at ae / be.  Each lane issues all its chunk
-  // loads into registers before the first LDS write, so they are in flight
-  // together.
+  // the pair in LDS, read in 16-byte chunks on a grid aligned in memory and
+  // stored whole: A's chunks from position 0 and B's after them, so A[a0]
+  // sits at oa and B[b0] at ob, and the windows end at ae and be.  Each lane
+  // issues all its chunk loads into registers before the first LDS write,
+  // so they are in flight together.
   constexpr int PV = (T / CH + 4 + NT - 1) / NT;  // ca + cb <= T / CH + 3
   const int sa = (int)(((uintptr_t)(A + a0) / sizeof(K)) & (CH - 1));
   const int sb = (int)(((uintptr_t)(B + b0) / sizeof(K)) & (CH - 1));
@@ -186,7 +186,8 @@ __global__ __launch_bounds__(kSetNT) void setop_tile_kernel(
 #pragma unroll
   for (int k = 0; k < PV; ++k) {
     const int c = tid + k * NT;
-    if (c < ca + cb) *reinterpret_cast<u32x4 *>(keys + c * CH) = *reinterpret_cast<u32x4 *>(stage[k]);
+    if (c < ca + cb)
+      *reinterpret_cast<u32x4 *>(keys + c * CH) = *reinterpret_cast<const u32x4 *>(stage[k]);
   }
   __syncthreads();
 
