@@ -110,3 +110,22 @@ def test_join_unsorted_inputs_stay_in_bounds(mp):
     assert (ib[:G] == -7).all() and (ib[G + cap:] == -7).all()
     assert (jb[:G] == -9).all() and (jb[G + cap:] == -9).all()
     assert int(host(cnt)[0]) >= 0
+
+
+@pytest.mark.parametrize("dt", [gen.U32, gen.U64])
+def test_join_unaligned_views(mp, orc, dt):
+    """A and B as views at element offsets that leave them off the 16-byte
+    grid: the rank tiles read their windows in chunks aligned in memory,
+    with element loads at the arrays' ends."""
+    from gpu_util import dev, host
+    g = np.random.default_rng(306)
+    npd = gen.NP_DTYPE[dt]
+    A = np.sort(g.integers(0, 30_000, 40_003)).astype(npd)
+    B = np.sort(g.integers(0, 30_000, 35_001)).astype(npd)
+    wi, wj, k = orc.join(A, B)
+    for oa, ob in ((1, 2), (3, 0), (0, 1), (2, 3)):
+        dA = dev(np.concatenate([np.zeros(oa, npd), A]))[oa:]
+        dB = dev(np.concatenate([np.zeros(ob, npd), B]))[ob:]
+        I, J = mp.join(dA, dB)
+        assert len(I) == k, (oa, ob, len(I), k)
+        assert np.array_equal(host(I), wi) and np.array_equal(host(J), wj), (oa, ob)
