@@ -94,7 +94,11 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
   // reads past the end of B's window
   __shared__ __align__(16) K keys[T + 4 * CH + VT + 1];
   __shared__ int32_t s_lo[T];   // per A key of the window: first B column, from b0
-  __shared__ int32_t s_cnt[T];  // per run head: B run length in the window, -1 past it
+  // per A key of the window: for the first key of a run of equal keys (a
+  // head), -(c + 2) with c the B run length of its value in the window (-1:
+  // past it); for any other key, the index of its head
+  __shared__ int32_t s_cnt[T];
+  __shared__ int32_t s_wmax[NT / 64];
   __shared__ int64_t s_big;     // the B run length of the value that goes past it
   __shared__ int64_t s_part[2][NT / 64];
   const int tid = threadIdx.x;
@@ -143,7 +147,10 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
   if (tid == 0) s_big = 0;
   __syncthreads();
   // the walk: each A key's first B column (ties take A, so every B key
-  // before it is smaller)
+  // before it is smaller).  All VT steps run: past the lane's own outputs
+  // the walk follows the same path as the next lane and records the same
+  // columns, and past the tile's end it takes nothing from A (LDS reads stay
+  // below be + VT + 1).
   {
     const int dl = tid * VT < n ? tid * VT : n;
     int lo, hi;
@@ -151,23 +158,56 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
     const int a = split_search<int>(
         dl, lo, hi, [&](int i) { return keys[oa + i]; }, [&](int j) { return keys[ob + j]; });
     int ai = oa + a, bi = ob + (dl - a);
-    const int steps = n - dl < VT ? n - dl : VT;
     K ka = keys[ai], kb = keys[bi];
 #pragma unroll
     for (int s = 0; s < VT; ++s) {
-      if (s < steps) {
-        const bool take_b = (bi < be) && (ai >= ae || kb < ka);
-        if (!take_b && ai < ae) s_lo[ai - oa] = bi - ob;
-        const int taken = take_b ? bi : ai;
-        ai = take_b ? ai : taken + 1;
-        bi = take_b ? taken + 1 : bi;
-        const K nxt = keys[taken + 1];
-        ka = take_b ? ka : nxt;
-        kb = take_b ? nxt : kb;
-      }
+      const bool take_b = (bi < be) && (ai >= ae || kb < ka);
+      if (!take_b && ai < ae) s_lo[ai - oa] = bi - ob;
+      const int taken = take_b ? bi : ai;
+      ai = take_b ? ai : taken + 1;
+      bi = take_b ? taken + 1 : bi;
+      const K nxt = keys[taken + 1];
+      ka = take_b ? ka : nxt;
+      kb = take_b ? nxt : kb;
     }
   }
-  __syncthreads();
+  // each A key's head (the first key of its run of equal keys in the
+  // window) by a segmented max-scan: lane t takes keys [t VT, t VT + VT),
+  // keeps the last head it has seen, and adds the last head of the lanes
+  // before it (a wavefront scan, then the wavefronts' maxima through LDS)
+  const int i0 = tid * VT;
+  int hd[VT];
+  {
+    int run = -1;
+    K prev = i0 > 0 && i0 <= wa ? keys[oa + i0 - 1] : K{};
+#pragma unroll
+    for (int j = 0; j < VT; ++j) {
+      const int i = i0 + j;
+      const K v = keys[oa + i];
+      const bool head = i < wa && (i == 0 || !key_equal(prev, v));
+      run = head ? i : run;
+      hd[j] = run;
+      prev = v;
+    }
+    const int lane = tid & 63;
+    int incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o);
+      incl = lane >= o && y > incl ? y : incl;
+    }
+    const int before = __shfl_up(incl, 1);
+    if (lane == 63) s_wmax[tid >> 6] = incl;
+    __syncthreads();
+    int carry = lane > 0 ? before : -1;
+    for (int w = 0; w < (tid >> 6); ++w) carry = s_wmax[w] > carry ? s_wmax[w] : carry;
+#pragma unroll
+    for (int j = 0; j < VT; ++j) hd[j] = hd[j] > carry ? hd[j] : carry;
+  }
+  // non-heads record their head's index
+#pragma unroll
+  for (int j = 0; j < VT; ++j)
+    if (i0 + j < wa && hd[j] != i0 + j) s_cnt[i0 + j] = hd[j];
   // run heads: the length of the B run of their value, galloping in the
   // window from the first column; only the value equal to the window's last
   // B key can go on past it
@@ -194,32 +234,28 @@ __global__ __launch_bounds__(kJoinNT) void join_rank_kernel(
       s_big = c + (upper_from(B, b1, nb, v) - b1);
       c = -1;
     }
-    s_cnt[i] = c;
+    s_cnt[i] = -(c + 2);
   }
   __syncthreads();
   // every A key of the window: its column, and its run head's count.  The
   // counts also add up per scan block of A: a window of at most T keys
-  // touches at most two blocks (blk0 and the next).
+  // touches at most two blocks, blk0 and the next, which starts at key
+  // i_split of the window.
   const int64_t blk0 = a0 / kScanBlock;
-  int64_t part0 = 0, part1 = 0;
+  const int64_t next_blk = (blk0 + 1) * kScanBlock - a0;
+  const int i_split = next_blk < wa ? (int)next_blk : wa;
+  int64_t part_all = 0, part1 = 0;
   for (int i = tid; i < wa; i += NT) {
-    const K v = keys[oa + i];
-    int h = i;
-    if (i > 0 && key_equal(keys[oa + i - 1], v)) {
-      int l = 0, r = i;  // first key of the window equal to v
-      while (l < r) {
-        const int m = (l + r) >> 1;
-        if (keys[oa + m] < v) l = m + 1; else r = m;
-      }
-      h = l;
-    }
-    const int c = s_cnt[h];
+    const int e = s_cnt[i];
+    const int c = -s_cnt[e >= 0 ? e : i] - 2;  // a non-head reads its head's entry
     const int rl = s_lo[i] < 0 ? 0 : (s_lo[i] > wb ? wb : s_lo[i]);
     lo_out[a0 + i] = b0 + rl;
     const int64_t cv = c >= 0 ? (int64_t)c : s_big;
     cnt_out[a0 + i] = cv;
-    if ((a0 + i) / kScanBlock == blk0) part0 += cv; else part1 += cv;
+    part_all += cv;
+    part1 += i >= i_split ? cv : 0;
   }
+  int64_t part0 = part_all - part1;
   // A keys between this window and the next tile's, which no tile visits
   // (none for sorted inputs, whose splits increase), get no pairs; so every
   // count is defined without clearing all of them first
