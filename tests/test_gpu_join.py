@@ -129,3 +129,21 @@ def test_join_unaligned_views(mp, orc, dt):
         I, J = mp.join(dA, dB)
         assert len(I) == k, (oa, ob, len(I), k)
         assert np.array_equal(host(I), wi) and np.array_equal(host(J), wj), (oa, ob)
+
+
+def test_join_workspace_alignment(mp, orc):
+    """The offsets array sits on 16 bytes inside the workspace whatever the
+    caller's 8-byte-aligned workspace and the parity of |A|: both parities,
+    with the workspace at a 16-byte and at an 8-byte (not 16-byte) address."""
+    from gpu_util import dev, host
+    g = np.random.default_rng(307)
+    for na in (20_001, 20_002):
+        A = np.sort(g.integers(0, 9_000, na)).astype(np.uint32)
+        B = np.sort(g.integers(0, 9_000, 17_003)).astype(np.uint32)
+        wi, wj, k = orc.join(A, B)
+        need = mp.lib().mp_join_workspace_bytes(na, len(B))
+        for shift in (0, 8):
+            ws = torch.empty(need + 16, dtype=torch.uint8, device="cuda")[shift:shift + need]
+            I, J = mp.join(dev(A), dev(B), ws=ws)
+            assert len(I) == k, (na, shift)
+            assert np.array_equal(host(I), wi) and np.array_equal(host(J), wj), (na, shift)
