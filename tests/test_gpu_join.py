@@ -147,3 +147,18 @@ def test_join_workspace_alignment(mp, orc):
             I, J = mp.join(dev(A), dev(B), ws=ws)
             assert len(I) == k, (na, shift)
             assert np.array_equal(host(I), wi) and np.array_equal(host(J), wj), (na, shift)
+
+
+def test_join_tile_boundaries(mp, orc):
+    """Total sizes at and next to whole numbers of 2048-key rank tiles, one
+    input empty or tiny, with few and with many distinct keys (runs of one
+    value then straddle the rank tiles and the emission tiles)."""
+    g = np.random.default_rng(308)
+    T = 2048
+    for total in (T - 1, T, T + 1, 2 * T, 5 * T - 1, 5 * T + 1):
+        for na in (0, 1, total // 3, total // 2, total - 1, total):
+            nb = total - na
+            for hi in (5, 1 << 20):
+                A = np.sort(g.integers(0, hi, na)).astype(np.uint32)
+                B = np.sort(g.integers(0, hi, nb)).astype(np.uint32)
+                _check(mp, orc, A, B)

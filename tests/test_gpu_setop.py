@@ -117,3 +117,21 @@ def test_set_op_unaligned_views(mp, orc, op, dt):
         assert k == len(want), (op, oa, ob, os_, k, len(want))
         assert full[os_:os_ + k].tobytes() == want.tobytes(), (op, oa, ob, os_)
         assert np.all(full[:os_] == 0x5A) and np.all(full[os_ + cap:] == 0x5A), (op, oa, ob, os_)
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("dt", [gen.U32, gen.U64])
+def test_set_op_tile_boundaries(mp, orc, op, dt):
+    """Total sizes at and next to whole numbers of tiles (12800 keys for
+    4-byte keys, 6656 for 8-byte keys, and small multiples), one input
+    empty or tiny, and runs of one value that straddle the tile ends."""
+    g = np.random.default_rng(90)
+    npd = gen.NP_DTYPE[dt]
+    T = 12800 if dt == gen.U32 else 6656
+    for total in (T - 1, T, T + 1, 2 * T, 3 * T - 1, 3 * T + 1):
+        for na in (0, 1, total // 3, total // 2, total - 1, total):
+            nb = total - na
+            for hi in (4, 1 << 20):
+                A = np.sort(g.integers(0, hi, na)).astype(npd)
+                B = np.sort(g.integers(0, hi, nb)).astype(npd)
+                _check(mp, orc, op, A, B)
