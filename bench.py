@@ -461,9 +461,15 @@ def leg_sort(args, ex):
         block = mp.sort_block_keys(torch.uint32)
         rounds = int(np.ceil(np.log2(max(1, n / block))))
         bytes_ = (1 + rounds) * n * 8
+        # the same sort counted as the 2048-key-block layout does it (one
+        # block pass, then a round per doubling from 2048 keys)
+        passes_2048 = 1 + int(np.ceil(np.log2(max(1, n / 2048))))
         res[name] = {"n": n, "ms": round(ms, 4), "Gkeys_s": round(n / ms / 1e6, 3),
                      "passes": 1 + rounds, "block_keys": block,
                      "hbm_frac": round(bytes_ / ms / 1e6 / HBM_PEAK_GBS, 4),
+                     "passes_with_2048_key_blocks": passes_2048,
+                     "hbm_frac_counting_2048_key_block_passes":
+                         round(passes_2048 * n * 8 / ms / 1e6 / HBM_PEAK_GBS, 4),
                      "blocksort_ms": round(bs[0] / max(1, bs[1]), 4),
                      "round_ms": round(rd[0] / max(1, rd[1]), 4),
                      "autotuned_config": {"nt": tuned[1], "vt": tuned[2]}, "hip_graph": True,
