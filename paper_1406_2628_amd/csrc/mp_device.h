@@ -42,6 +42,37 @@ __device__ __forceinline__ I split_search(I d, I lo, I hi, GA ga, GB gb) {
   return lo;
 }
 
+// Split on diagonal d restricted to the candidate interval [lo, hi), found
+// by the 64 lanes of the calling wavefront (every lane returns the same
+// value).  Each round probes 64 interior points and keeps the gap where the
+// predicate B[d-1-a] < A[a] first turns true (it is monotone in a,
+// Corollary 12).
+template <typename GA, typename GB>
+__device__ int64_t wave_split_search(int64_t d, int64_t lo, int64_t hi, GA ga, GB gb) {
+  const int lane = threadIdx.x & 63;
+  while (lo < hi) {
+    const int64_t span = hi - lo;
+    if (span <= 64) {
+      const int64_t p = lo + lane;
+      const bool pred = lane < span && (gb(d - 1 - p) < ga(p));
+      const uint64_t m = __ballot(pred);
+      return m ? lo + (int64_t)(__ffsll((long long)m) - 1) : hi;
+    }
+    const int64_t p = lo + ((int64_t)(lane + 1) * span) / 65;
+    const bool pred = gb(d - 1 - p) < ga(p);
+    const uint64_t m = __ballot(pred);
+    if (m == 0) {
+      lo = lo + ((int64_t)64 * span) / 65 + 1;
+    } else {
+      const int f = __ffsll((long long)m) - 1;
+      const int64_t pf = lo + ((int64_t)(f + 1) * span) / 65;
+      lo = f == 0 ? lo : lo + ((int64_t)f * span) / 65 + 1;
+      hi = pf;
+    }
+  }
+  return lo;
+}
+
 // The same search with G lanes per diagonal (G a power of two, 2..64): the
 // group is an aligned block of G lanes of one wavefront holding the same d,
 // lo and hi.  Each round its lanes probe G points that cut [lo, hi) G + 1

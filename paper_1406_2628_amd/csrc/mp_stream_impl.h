@@ -72,37 +72,6 @@ struct PairArgs {
   unsigned long long *checksum;  // no-store launches: sum of S[i] * (i + 1) added here
 };
 
-// Split on diagonal d of the grid A'[lo_a ...] x B' restricted to candidate
-// interval [lo, hi), found by the 64 lanes of the calling wavefront (every
-// lane returns the same value).  Each round probes 64 interior points and
-// keeps the gap where the predicate B'[d-1-a] < A'[a] first turns true (it
-// is monotone in a, Corollary 12).
-template <typename GA, typename GB>
-__device__ int64_t wave_split_search(int64_t d, int64_t lo, int64_t hi, GA ga, GB gb) {
-  const int lane = threadIdx.x & 63;
-  while (lo < hi) {
-    const int64_t span = hi - lo;
-    if (span <= 64) {
-      const int64_t p = lo + lane;
-      const bool pred = lane < span && (gb(d - 1 - p) < ga(p));
-      const uint64_t m = __ballot(pred);
-      return m ? lo + (int64_t)(__ffsll((long long)m) - 1) : hi;
-    }
-    const int64_t p = lo + ((int64_t)(lane + 1) * span) / 65;
-    const bool pred = gb(d - 1 - p) < ga(p);
-    const uint64_t m = __ballot(pred);
-    if (m == 0) {
-      lo = lo + ((int64_t)64 * span) / 65 + 1;
-    } else {
-      const int f = __ffsll((long long)m) - 1;
-      const int64_t pf = lo + ((int64_t)(f + 1) * span) / 65;
-      lo = f == 0 ? lo : lo + ((int64_t)f * span) / 65 + 1;
-      hi = pf;
-    }
-  }
-  return lo;
-}
-
 // Value of the first active lane (wave-uniform).
 __device__ __forceinline__ int64_t first_lane64(int64_t v) {
   const uint64_t u = (uint64_t)v;

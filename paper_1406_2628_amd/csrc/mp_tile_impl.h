@@ -38,7 +38,7 @@
 namespace mp {
 
 enum TileKind { kTileSingle = 0, kTileRuns = 1, kTileBatch = 2 };
-enum TileSrc { kTileHeader = 0, kTileSplitArray = 1 };
+enum TileSrc { kTileHeader = 0, kTileSplitArray = 1, kTileSearch = 2 };
 
 template <typename K>
 struct TileArgs {
@@ -380,7 +380,27 @@ __global__ __launch_bounds__(NT) void merge_tile_kernel(TileArgs<K> P) {
     cnt = pn + 2 - pf;
   }
   const bool use_tab = KIND == kTileBatch && cnt <= kPairTab;
-  if constexpr (SRC == kTileSplitArray) {
+  if constexpr (SRC == kTileSearch) {
+    // one launch for a merge whose tiles all run at once: the tile finds its
+    // own two splits (Algorithm 1's first step), wavefront 0 on its start
+    // diagonal and wavefront 1 on its end diagonal, each by a 64-way search
+    // in global memory (single pairs only)
+    static_assert(KIND == kTileSingle && NT >= 128, "two wavefronts per single-pair tile");
+    __shared__ int64_t s_ends[2];
+    const int w = tid >> 6;
+    if (w < 2) {
+      const int64_t d = d0 + (w == 0 ? 0 : n);
+      int64_t lo, hi;
+      diag_range<int64_t>(d, NA, NB, lo, hi);
+      const int64_t a = wave_split_search(
+          d, lo, hi, [&](int64_t i) { return P.A[i]; }, [&](int64_t j) { return P.B[j]; });
+      if ((tid & 63) == 0) s_ends[w] = a;
+    }
+    __syncthreads();
+    a0 = s_ends[0];
+    b0 = d0 - a0;
+    a1 = s_ends[1];
+  } else if constexpr (SRC == kTileSplitArray) {
     // the caller's splits: a0 kept on the start diagonal inside the grid and
     // the A count in its valid range, whatever the values (for the true
     // splits of sorted inputs both clamps change nothing)
@@ -706,6 +726,7 @@ template <typename K, int KIND, int SRC>
 static hipError_t launch_tiles_any(TileCfg cfg, const TileArgs<K> &P, bool vload, hipStream_t s) {
   // (merges on given splits and batches carry keys only)
   constexpr bool KV_OK = SRC == kTileHeader && KIND != kTileBatch;
+  static_assert(SRC != kTileSearch, "the one-launch path has its own dispatch");
   const bool kv = KV_OK && P.Sv != nullptr;
 #define MP_TILE_CASE(NT_, VT_)                                                             \
   if (cfg.nt == NT_ && cfg.vt == VT_) {                                                    \
@@ -727,6 +748,29 @@ static hipError_t launch_tiles_any(TileCfg cfg, const TileArgs<K> &P, bool vload
 
 static inline bool tile_aligned16(const void *p) { return ((uintptr_t)p % 16) == 0; }
 
+// A merge small enough that all its tiles run at once (at most two per
+// compute unit) on one of the small built-in shapes takes one launch: each
+// tile searches its own splits, so no split kernel runs before it.
+template <typename K, bool KV>
+static hipError_t launch_tiles_search(TileCfg cfg, TileArgs<K> P, bool vload, hipStream_t s) {
+#define MP_SEARCH_CASE(NT_, VT_)                                                           \
+  if (cfg.nt == NT_ && cfg.vt == VT_) {                                                    \
+    P.n_tiles = (P.N + NT_ * VT_ - 1) / (NT_ * VT_);                                       \
+    KernelTimer timer("tile_merge", s);                                                    \
+    if (vload)                                                                             \
+      hipLaunchKernelGGL((merge_tile_kernel<K, KV, NT_, VT_, kTileSingle, kTileSearch, true>), \
+                         dim3((unsigned)P.n_tiles), dim3(NT_), 0, s, P);                    \
+    else                                                                                   \
+      hipLaunchKernelGGL((merge_tile_kernel<K, KV, NT_, VT_, kTileSingle, kTileSearch, false>), \
+                         dim3((unsigned)P.n_tiles), dim3(NT_), 0, s, P);                    \
+    return hipGetLastError();                                                              \
+  }
+  MP_SEARCH_CASE(256, 16)
+  MP_SEARCH_CASE(256, 8)
+#undef MP_SEARCH_CASE
+  return hipErrorNotSupported;
+}
+
 template <typename K>
 hipError_t launch_merge_tiles(TileCfg cfg, const K *A, const uint32_t *Av, int64_t na,
                               const K *B, const uint32_t *Bv, int64_t nb, K *S, uint32_t *Sv,
@@ -737,6 +781,11 @@ hipError_t launch_merge_tiles(TileCfg cfg, const K *A, const uint32_t *Av, int64
   const bool kv = Sv != nullptr;
   const bool vload = tile_aligned16(A) && tile_aligned16(B) &&
                      (!kv || (tile_aligned16(Av) && tile_aligned16(Bv)));
+  const int64_t T = (int64_t)cfg.nt * cfg.vt;
+  const bool small_shape = cfg.nt == 256 && (cfg.vt == 16 || cfg.vt == 8);
+  if (small_shape && P.N > 0 && (P.N + T - 1) / T <= 2 * (int64_t)device_cu_count())
+    return kv ? launch_tiles_search<K, true>(cfg, P, vload, s)
+              : launch_tiles_search<K, false>(cfg, P, vload, s);
   return launch_tiles_any<K, kTileSingle, kTileHeader>(cfg, P, vload, s);
 }
 
