@@ -151,3 +151,36 @@ def test_copy_reference(mp):
     mp.copy(x, y)
     torch.cuda.synchronize()
     assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("dt", [gen.U32, gen.U64])
+def test_short_last_tile(mp, orc, dt):
+    """Per-tile merges (split kernel, then tiles; 256 x 15 tiles) whose last
+    tile is shorter than the 32-byte header that carries a tile's splits:
+    that tile steps the path back from the grid's end instead.  Uniform
+    keys and heavy duplicates (backwards, ties go to B), keys and
+    key-value."""
+    from gpu_util import dev, host, first_mismatch
+    mp.set_config("merge", 1, 256, 15)
+    try:
+        for r in (1, 3, 7):
+            N = 3 * 3840 + r
+            for frac in (0.3, 0.7):
+                na = int(N * frac)
+                nb = N - na
+                for dups in (False, True):
+                    if dups:
+                        g = np.random.default_rng(600 + r)
+                        npd = gen.NP_DTYPE[dt]
+                        A = np.sort(g.integers(0, 5, na)).astype(npd)
+                        B = np.sort(g.integers(0, 5, nb)).astype(npd)
+                    else:
+                        A, B = gen.uniform_pair(na, nb, 500 + r, dt)
+                    got = host(mp.merge(dev(A), dev(B)))
+                    assert first_mismatch(got, orc.merge(A, B)) is None, (r, frac, dups)
+                    va, vb = gen.index_payload(na, nb)
+                    gk, gv = mp.merge_kv(dev(A), dev(va), dev(B), dev(vb))
+                    wk, wv = orc.merge_kv(A, va, B, vb)
+                    assert first_mismatch(host(gk), wk) is None and first_mismatch(host(gv), wv) is None
+    finally:
+        mp.set_config("merge", None)
