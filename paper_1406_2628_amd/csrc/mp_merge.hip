@@ -7,6 +7,26 @@
 
 namespace mp {
 
+// The split on diagonal d by binary lifting from the aligned origin 0: x
+// counts the positions known to fail Algorithm 2's test, and each power of
+// two, largest first, is added when the position it reaches still fails
+// (positions below lo fail by the grid's bounds and are not read; none at
+// or past hi is probed; the test is monotone, Corollary 12).  On diagonals
+// that are multiples of a power of two T, every probe at a step of at least
+// T falls on a multiple of T (less one) in both inputs, so neighbouring
+// diagonals share those probes through the caches.
+template <typename K>
+__device__ __forceinline__ int64_t aligned_split(const K *__restrict__ A, const K *__restrict__ B,
+                                                 int64_t d, int64_t lo, int64_t hi) {
+  int64_t x = 0;
+  if (hi <= 0) return 0;
+  for (int64_t bit = (int64_t)1 << (63 - __clzll((unsigned long long)hi)); bit > 0; bit >>= 1) {
+    const int64_t c = x + bit - 1;
+    if (c < hi && (c < lo || !(B[d - 1 - c] < A[c]))) x += bit;
+  }
+  return x;
+}
+
 template <typename K>
 __global__ void partition_kernel(const K *__restrict__ A, int64_t na,
                                  const K *__restrict__ B, int64_t nb,
@@ -19,9 +39,14 @@ __global__ void partition_kernel(const K *__restrict__ A, int64_t na,
   d = d < 0 ? 0 : (d > n ? n : d);
   int64_t lo, hi;
   diag_range<int64_t>(d, na, nb, lo, hi);
-  a_split[k] = split_search<int64_t>(
-      d, lo, hi, [&](int64_t i) { return A[i]; },
-      [&](int64_t j) { return B[j]; });
+  // diagonals k * T with T a power of two: the aligned search (identical
+  // splits); any other diagonals: the plain lower-bound search
+  if (!diag && tile > 0 && (tile & (tile - 1)) == 0)
+    a_split[k] = aligned_split(A, B, d, lo, hi);
+  else
+    a_split[k] = split_search<int64_t>(
+        d, lo, hi, [&](int64_t i) { return A[i]; },
+        [&](int64_t j) { return B[j]; });
 }
 
 // G lanes per diagonal (group_split_search); lane 0 of each group writes.
