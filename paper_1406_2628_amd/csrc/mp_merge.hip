@@ -11,10 +11,11 @@ namespace mp {
 // counts the positions known to fail Algorithm 2's test, and each power of
 // two, largest first, is added when the position it reaches still fails
 // (positions below lo fail by the grid's bounds and are not read; none at
-// or past hi is probed; the test is monotone, Corollary 12).  On diagonals
-// that are multiples of a power of two T, every probe at a step of at least
-// T falls on a multiple of T (less one) in both inputs, so neighbouring
-// diagonals share those probes through the caches.
+// or past hi is probed; the test is monotone, Corollary 12).  A probe's A
+// index depends only on the steps taken so far, so diagonals that share them
+// share the probe; on diagonals that are multiples of a power of two T, every
+// probe at a step of at least T also falls on a multiple of T in B.  Both
+// come from the caches for neighbouring diagonals.
 template <typename K>
 __device__ __forceinline__ int64_t aligned_split(const K *__restrict__ A, const K *__restrict__ B,
                                                  int64_t d, int64_t lo, int64_t hi) {
@@ -39,9 +40,10 @@ __global__ void partition_kernel(const K *__restrict__ A, int64_t na,
   d = d < 0 ? 0 : (d > n ? n : d);
   int64_t lo, hi;
   diag_range<int64_t>(d, na, nb, lo, hi);
-  // diagonals k * T with T a power of two: the aligned search (identical
-  // splits); any other diagonals: the plain lower-bound search
-  if (!diag && tile > 0 && (tile & (tile - 1)) == 0)
+  // tile boundaries k * T: the aligned search (identical splits; the A
+  // probes are shared for any T, the B probes too when T is a power of
+  // two); diagonals the caller lists: the plain lower-bound search
+  if (!diag && tile > 0)
     a_split[k] = aligned_split(A, B, d, lo, hi);
   else
     a_split[k] = split_search<int64_t>(
